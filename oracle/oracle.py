@@ -1,0 +1,301 @@
+"""ctypes wrapper around the plain-C oracle (``jabba_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.
+
+The C file is compiled with gcc ``-O2 -ffp-contract=off -fno-fast-math`` so
+that each floating-point operation is a single correctly rounded binary64
+operation in source order.  Inputs and outputs are numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "build_oracle",
+    "lib",
+    "OracleError",
+    "count_domains",
+    "domains",
+    "compress",
+    "tree_sum",
+    "exact_sum",
+    "scaling",
+    "sort_order",
+    "blocks",
+    "aggregate_sorted",
+    "digitize",
+    "Digitized",
+    "reconstruct",
+    "reconstruct_pieces",
+    "encode",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jabba_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_SO = os.path.join(_BUILD, "libjabba_oracle.so")
+_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11", "-shared", "-fPIC"]
+_lock = threading.Lock()
+_lib = None
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile the oracle shared library (always when ``force``).
+
+    ``JABBA_ORACLE_SO`` names a prebuilt oracle library to load instead; the
+    mutation tests use it to run the pins against deliberately broken copies.
+    """
+    override = os.environ.get("JABBA_ORACLE_SO")
+    if override and not force:
+        return override
+    os.makedirs(_BUILD, exist_ok=True)
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", *_FLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+
+
+def _nullable(tp):
+    base = np.ctypeslib.ndpointer(tp, flags="C")
+
+    class _N(base):  # type: ignore[misc, valid-type]
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return base.from_param(obj)
+
+    return _N
+
+
+_i64n = _nullable(np.int64)
+_f64n = _nullable(np.float64)
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            L = C.CDLL(build_oracle())
+            L.jo_count_domains.restype = C.c_int64
+            L.jo_count_domains.argtypes = [_i64p, C.c_int64, C.c_int32]
+            L.jo_domains.restype = C.c_int
+            L.jo_domains.argtypes = [_i64p, C.c_int64, C.c_int32, _i64p, _i64p, _i64p]
+            L.jo_compress.restype = C.c_int64
+            L.jo_compress.argtypes = [_f64p, _i64p, C.c_int64, C.c_int32, C.c_double, C.c_int32, _i32p, _f64p,
+                                      _i64p]
+            L.jo_tree_sum.restype = C.c_double
+            L.jo_tree_sum.argtypes = [_f64p, C.c_int64]
+            L.jo_exact_sum.restype = C.c_double
+            L.jo_exact_sum.argtypes = [_f64p, C.c_int64]
+            L.jo_scaling.restype = C.c_int
+            L.jo_scaling.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), _f64n, _f64n, _f64n]
+            L.jo_sort_order.restype = None
+            L.jo_sort_order.argtypes = [_f64p, C.c_int64, _i64p]
+            L.jo_blocks.restype = C.c_int64
+            L.jo_blocks.argtypes = [_f64p, C.c_int64, C.c_int64, _i64p]
+            L.jo_aggregate_sorted.restype = None
+            L.jo_aggregate_sorted.argtypes = [_f64p, _f64p, _f64p, C.c_int64, C.c_double, _i64p]
+            L.jo_digitize.restype = C.c_int64
+            L.jo_digitize.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64,
+                                      _i32p, _i64n, _i64n, C.POINTER(C.c_int64), _i64n, _f64n, _f64n, _f64n,
+                                      _f64n, _f64n, _i64n, C.POINTER(C.c_int64)]
+            L.jo_reconstruct_size.restype = C.c_int
+            L.jo_reconstruct_size.argtypes = [_i32p, _i64p, _i64p, C.c_int64, _f64p, C.c_int64, _i64p]
+            L.jo_reconstruct.restype = C.c_int
+            L.jo_reconstruct.argtypes = [_i32p, _i64p, _i64p, C.c_int64, _f64p, _f64p, _f64p, C.c_int64, _i64p,
+                                         _f64p, _i64n, _f64n, _f64n, _i64n]
+            L.jo_reconstruct_pieces.restype = C.c_int
+            L.jo_reconstruct_pieces.argtypes = [_i32p, _f64p, _i64p, C.c_int64, _f64p, _i64p, _f64p]
+            L.jo_encode.restype = C.c_int
+            L.jo_encode.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_double, _f64p, _f64p,
+                                    C.c_int64, _i32p]
+            _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise OracleError(f"{what} failed with status {rc}")
+    return rc
+
+
+def count_domains(series_off, D: int) -> int:
+    so = _i64(series_off)
+    return int(lib().jo_count_domains(so, so.size - 1, D))
+
+
+def domains(series_off, D: int):
+    """Domain table: (series, first point, number of intervals) per domain."""
+    so = _i64(series_off)
+    m = count_domains(so, D)
+    ds, st, ni = (np.zeros(m, np.int64) for _ in range(3))
+    _check(lib().jo_domains(so, so.size - 1, D, ds, st, ni), "domains")
+    return ds, st, ni
+
+
+def compress(values, series_off, D: int, tol: float, max_len: int = 0):
+    """Greedy compression of every domain.  Returns (len i32, inc f64, piece_off i64)."""
+    v = _f64(values)
+    so = _i64(series_off)
+    ns = so.size - 1
+    cap = int(np.maximum(np.diff(so) - 1, 0).sum())
+    ln = np.zeros(max(cap, 1), np.int32)
+    inc = np.zeros(max(cap, 1), np.float64)
+    po = np.zeros(ns + 1, np.int64)
+    n = _check(lib().jo_compress(v, so, ns, int(D), float(tol), int(max_len), ln, inc, po), "compress")
+    return ln[:n].copy(), inc[:n].copy(), po
+
+
+def tree_sum(a) -> float:
+    a = _f64(a)
+    return float(lib().jo_tree_sum(a, a.size))
+
+
+def exact_sum(a) -> float:
+    a = _f64(a)
+    return float(lib().jo_exact_sum(a, a.size))
+
+
+def scaling(length, inc, scl: float = 1.0):
+    """Returns (sigma_len, sigma_inc, x, y, key)."""
+    ln, ic = _i32(length), _f64(inc)
+    n = ln.size
+    sl, si = C.c_double(), C.c_double()
+    x, y, k = (np.zeros(n) for _ in range(3))
+    _check(lib().jo_scaling(ln, ic, n, float(scl), C.byref(sl), C.byref(si), x, y, k), "scaling")
+    return sl.value, si.value, x, y, k
+
+
+def sort_order(key):
+    key = _f64(key)
+    perm = np.zeros(key.size, np.int64)
+    lib().jo_sort_order(key, key.size, perm)
+    return perm
+
+
+def blocks(sorted_key, B: int):
+    sk = _f64(sorted_key)
+    bs = np.zeros(sk.size + 2, np.int64)
+    m = int(lib().jo_blocks(sk, sk.size, int(B), bs))
+    return bs[: m + 1].copy()
+
+
+def aggregate_sorted(sx, sy, skey, alpha: float):
+    """Serial greedy aggregation over presorted arrays; returns start position per point."""
+    sx, sy, sk = _f64(sx), _f64(sy), _f64(skey)
+    lab = np.zeros(sx.size, np.int64)
+    lib().jo_aggregate_sorted(sx, sy, sk, sx.size, float(alpha), lab)
+    return lab
+
+
+@dataclass
+class Digitized:
+    symbols: np.ndarray
+    k: int
+    sigma_len: float
+    sigma_inc: float
+    scl: float
+    alpha: float
+    center_len: np.ndarray
+    center_inc: np.ndarray
+    cx: np.ndarray
+    cy: np.ndarray
+    count: np.ndarray
+    perm: np.ndarray
+    local_start: np.ndarray
+    n_starts: int
+    gmap: np.ndarray
+    n_blocks: int
+
+
+def digitize(length, inc, alpha: float, scl: float = 1.0, B: int = 4096, capacity: int | None = None) -> Digitized:
+    """Two-stage digitization and dictionary (see jo_digitize)."""
+    ln, ic = _i32(length), _f64(inc)
+    n = ln.size
+    cap = n if capacity is None else int(capacity)
+    sym = np.zeros(max(n, 1), np.int32)
+    perm = np.zeros(max(n, 1), np.int64)
+    lst = np.zeros(max(n, 1), np.int64)
+    gmap = np.zeros(max(n, 1), np.int64)
+    sig = np.zeros(2)
+    cl, ci, cx, cy = (np.zeros(max(cap, 1)) for _ in range(4))
+    cnt = np.zeros(max(cap, 1), np.int64)
+    g = C.c_int64()
+    nb = C.c_int64()
+    k = _check(lib().jo_digitize(ln, ic, n, float(alpha), float(scl), int(B), cap, sym, perm, lst, C.byref(g),
+                                 gmap, sig, cl, ci, cx, cy, cnt, C.byref(nb)), "digitize")
+    G = g.value
+    return Digitized(sym[:n].copy(), int(k), float(sig[0]), float(sig[1]), float(scl), float(alpha),
+                     cl[:k].copy(), ci[:k].copy(), cx[:k].copy(), cy[:k].copy(), cnt[:k].copy(), perm[:n].copy(),
+                     lst[:n].copy(), int(G), gmap[:G].copy(), int(nb.value))
+
+
+def reconstruct(symbols, piece_off, series_off, t0, center_len, center_inc, orig=None):
+    """Inverse symbolization.  Returns (out f64, out_off i64, lhat i64, sse f64[ns], cnt i64[ns])."""
+    sym, po, so = _i32(symbols), _i64(piece_off), _i64(series_off)
+    cl, ci, t0 = _f64(center_len), _f64(center_inc), _f64(t0)
+    ns = po.size - 1
+    k = cl.size
+    oo = np.zeros(ns + 1, np.int64)
+    _check(lib().jo_reconstruct_size(sym, po, so, ns, cl, k, oo), "reconstruct_size")
+    out = np.zeros(max(int(oo[-1]), 1))
+    lhat = np.zeros(max(sym.size, 1), np.int64)
+    sse = np.zeros(max(ns, 1))
+    cnt = np.zeros(max(ns, 1), np.int64)
+    og = None if orig is None else _f64(orig)
+    _check(lib().jo_reconstruct(sym, po, so, ns, t0, cl, ci, k, oo, out, lhat, og,
+                                sse if og is not None else None, cnt if og is not None else None),
+           "reconstruct")
+    return out[: oo[-1]].copy(), oo, lhat[: sym.size].copy(), sse[:ns].copy(), cnt[:ns].copy()
+
+
+def reconstruct_pieces(length, inc, piece_off, t0):
+    """Polyline straight from (len, inc); returns (out, out_off)."""
+    ln, ic, po, t0 = _i32(length), _f64(inc), _i64(piece_off), _f64(t0)
+    ns = po.size - 1
+    oo = np.zeros(ns + 1, np.int64)
+    for s in range(ns):
+        a, b = po[s], po[s + 1]
+        oo[s + 1] = oo[s] + (1 + int(ln[a:b].sum()) if b > a else 1)
+    out = np.zeros(max(int(oo[-1]), 1))
+    _check(lib().jo_reconstruct_pieces(ln, ic, po, ns, t0, oo, out), "reconstruct_pieces")
+    return out[: oo[-1]].copy(), oo
+
+
+def encode(length, inc, sigma_len, sigma_inc, scl, cx, cy):
+    ln, ic, cx, cy = _i32(length), _f64(inc), _f64(cx), _f64(cy)
+    sym = np.zeros(max(ln.size, 1), np.int32)
+    _check(lib().jo_encode(ln, ic, ln.size, float(sigma_len), float(sigma_inc), float(scl), cx, cy, cx.size, sym),
+           "encode")
+    return sym[: ln.size].copy()
