@@ -1,0 +1,326 @@
+/*
+ * jabba.h — C ABI of the MI355X (gfx950) joint-symbolic-approximation library.
+ *
+ * The calls follow the statement of the problem in arXiv 2401.00109:
+ * Algorithm 1 takes a collection of series, a compression tolerance and a
+ * digitization method and returns symbols plus a shared dictionary; Table 1
+ * (table:ABBA) fixes the objects: series T, pieces P = [(len, inc)], symbols A,
+ * and the inverse chain P~ -> P^ -> T^.
+ *
+ *   compress(series, tol)      -> pieces            (Sec. 3.1, Eq. compress; Sec. 4.1)
+ *   digitize(pieces, alpha)    -> dictionary, symbols (Sec. 3.2; Sec. 5 two-stage)
+ *   encode(pieces, dictionary) -> symbols           (Sec. 3.2, nearest center)
+ *   reconstruct(symbols, dictionary, t0) -> series  (Sec. 3.3)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers are DEVICE pointers unless the argument name ends in "_host".
+ *    The caller allocates and owns every buffer, including workspaces and the
+ *    dictionary arrays; nothing on these paths allocates device memory.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the legacy
+ *    default stream).  A return of JABBA_OK means the work was enqueued.
+ *  - Counts produced on the device (number of pieces, symbols, output points)
+ *    stay in device memory; no call synchronises the host, except
+ *    jabba_workspace_status and the plan/tuning helpers that say so.
+ *  - Host-detected errors are returned immediately and nothing is enqueued.
+ *    Device-detected errors (a non-finite input value, a dictionary that is
+ *    too small) are OR-ed into a status word held in the call's workspace;
+ *    read it with jabba_workspace_status after the stream has run.
+ *  - Layouts: values of all series concatenated, series s occupying
+ *    [series_off[s], series_off[s+1]); pieces of all series concatenated in
+ *    canonical order (series, domain, position), series s occupying
+ *    [piece_off[s], piece_off[s+1]).  len is int32, inc/values are binary64.
+ *  - Arithmetic is binary64 everywhere a decision is taken (piece ends,
+ *    groups, symbols), with no fused multiply-add, in the operation order
+ *    documented at each call, so results are bit-identical to a plain
+ *    sequential CPU evaluation of the same formulas.
+ *  - Limits: fewer than 2^31 pieces per call; series lengths < 2^31.
+ *  - Thread safety: calls on distinct streams with distinct buffers (and
+ *    distinct workspaces) may run concurrently.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef JABBA_H
+#define JABBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JABBA_ABI_VERSION 1
+
+enum jabba_status {
+    JABBA_OK = 0,
+    JABBA_EINVAL = -1,      /* bad argument (sizes, tolerances, null pointers)          */
+    JABBA_ENOMEM = -2,      /* workspace smaller than the size query returned            */
+    JABBA_EHIP = -3,        /* a HIP runtime call failed                                 */
+    JABBA_ECAPACITY = -4,   /* device: more symbols than the dictionary capacity         */
+    JABBA_ENONFINITE = -5,  /* device: a series value is NaN or infinite                 */
+    JABBA_EOVERFLOW = -6,   /* a count exceeds the 2^31 limit                            */
+    JABBA_ENODEV = -7       /* no gfx950 device is current                               */
+};
+
+/* Library ABI version (JABBA_ABI_VERSION of the build). */
+int jabba_abi_version(void);
+
+/* Static, human-readable text for a status code. */
+const char *jabba_status_str(int status);
+
+/*
+ * Launch-shape knobs.  They never change results, only speed (the autotuner
+ * checks that every variant it times returns bit-identical outputs).
+ * A zero field means "library default".  Pass NULL for all defaults.
+ */
+typedef struct jabba_tuning {
+    int32_t lanes_per_domain; /* compress: lanes that test candidate end points of one
+                                 domain together; 1, 2, 4, 8, 16, 32 or 64 (64 = one
+                                 wavefront per domain)                                  */
+    int32_t waves_per_block;  /* compress: wavefronts per workgroup, 1..16              */
+    int32_t blocks_per_cu;    /* compress: persistent workgroups per compute unit, 1..32 */
+    int32_t stage1_waves;     /* digitize Stage I: wavefronts per workgroup (one block
+                                 of sorted pieces per wavefront), 1..16                 */
+    int32_t reserved[4];
+} jabba_tuning;
+
+/*
+ * Dictionary (Sec. 3.2: the symbolic centers; Alg. 1 output D).  All arrays
+ * are caller-allocated device memory with `capacity` entries.
+ *   params[0] = sigma_len, params[1] = sigma_inc  (population std of the
+ *               training pieces, a zero deviation replaced by 1),
+ *   params[2] = scl, params[3] = alpha.
+ *   k[0]      = number of symbols (written by jabba_digitize).
+ *   center_len[c], center_inc[c] = mean (len, inc) of the members of symbol c;
+ *   cx[c] = scl*(center_len/sigma_len), cy[c] = center_inc/sigma_inc;
+ *   count[c] = number of member pieces.
+ */
+typedef struct jabba_dict {
+    int64_t capacity;
+    double *params;
+    int64_t *k;
+    double *center_len;
+    double *center_inc;
+    double *cx;
+    double *cy;
+    int64_t *count;
+} jabba_dict;
+
+/* ------------------------------------------------------------------------ */
+/* Compression: Alg. 1 Phases I-II (Sec. 4.1) with the ABBA compression of    */
+/* Sec. 3.1 (Eq. compress).                                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Workspace bytes for jabba_compress / jabba_compress_plain with these sizes.
+ * n_series >= 0, total_points = series_off[n_series] >= 0, D >= 1.
+ */
+int jabba_compress_workspace(int64_t n_series, int64_t total_points, int32_t D, size_t *bytes);
+
+/*
+ * Phase I: every series is cut into domains of D unit intervals; domain d of
+ * a series with n points covers points [d*D, min((d+1)*D, n-1)], so adjacent
+ * domains share an end point (Sec. 4.1.1).  Phase II: each domain is
+ * compressed independently (Sec. 4.1.2) by greedy first-failure growth: from
+ * piece start s, candidate length c = 2, 3, ... is accepted while
+ *     sum_{k=1}^{c-1} (t_s + slope*k - t_{s+k})^2 <= (c-1)*(tol*tol),
+ *     slope = (t_{s+c} - t_s)/c, terms added in ascending k,
+ * and the piece ends just before the first rejected candidate, at the domain
+ * end, or at max_len (> 0).  Each piece is (len, inc = t_{s+len} - t_s).
+ * Pieces are concatenated in canonical order (Sec. 4.1.3).
+ *
+ *  values[total_points], series_off[n_series+1] (non-decreasing, [0] = 0)
+ *  len, inc: capacity sum_s max(n_s - 1, 0) (the worst case; <= total_points)
+ *  piece_off[n_series+1]: out, piece offsets per series
+ *  n_pieces[1]: out, total number of pieces (int64)
+ *  tuning: NULL or launch knobs; tol >= 0 finite; max_len >= 0 (0 = none).
+ * Device status: JABBA_ENONFINITE if a value is NaN/Inf (pieces are then
+ * unspecified).  Returns JABBA_EINVAL for bad sizes, JABBA_ENOMEM if
+ * workspace_bytes is below jabba_compress_workspace.
+ */
+int jabba_compress(const double *values, const int64_t *series_off, int64_t n_series, int64_t total_points,
+                   int32_t D, double tol, int32_t max_len, const jabba_tuning *tuning, int32_t *len, double *inc,
+                   int64_t *piece_off, int64_t *n_pieces, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * The same computation launched the plain way: one kernel launch per series
+ * (grid = that series' domains, one wavefront per domain, 64 candidate end
+ * points per round), no work queue.  Kept as the per-domain-launch baseline
+ * the batched form is compared with.  series_off_host is a host copy of
+ * series_off.  Same outputs, bit for bit, as jabba_compress.
+ */
+int jabba_compress_plain(const double *values, const int64_t *series_off, const int64_t *series_off_host,
+                         int64_t n_series, int32_t D, double tol, int32_t max_len, int32_t *len, double *inc,
+                         int64_t *piece_off, int64_t *n_pieces, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Digitization: Alg. 1 Phase III with the two-stage aggregation of Sec. 5.   */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes for jabba_digitize with at most max_pieces pieces. */
+int jabba_digitize_workspace(int64_t max_pieces, int32_t B, size_t *bytes);
+
+/*
+ * 1. Scaling (Sec. 3.2, Eq. tupseq2): sigma_len from exact int64 sums of len
+ *    and len^2 (var = S2/N - (S1/N)^2, clamped at 0); sigma_inc by two passes
+ *    of a balanced pairwise sum (leaves in canonical order, zero-padded to a
+ *    power of two); zero deviations replaced by 1;
+ *    x = scl*(len/sigma_len), y = inc/sigma_inc, key = sqrt(x*x + y*y).
+ * 2. Sort: ascending key, ties by canonical index (Sec. 5, global sorting
+ *    index).
+ * 3. Blocks: B sorted pieces per block, each cut moved forward past equal
+ *    keys (Sec. 5, "M contiguous blocks").
+ * 4. Stage I: in every block, greedy aggregation in sorted order: an
+ *    unassigned piece p starts a group; later pieces q are scanned while
+ *    key_q - key_p <= alpha, and an unassigned q joins when
+ *    (x_q - x_p)^2 + (y_q - y_p)^2 <= alpha*alpha.
+ * 5. Stage II: the same aggregation over all Stage I starting points, which
+ *    are already in sorted order.
+ * 6. Label propagation (Eq. l_i = l~_g): symbol of a piece = global group of
+ *    its local start.  Symbols are numbered by sorted position of the global
+ *    start.
+ * 7. Dictionary: count and exact int64 length sum per symbol; center_len =
+ *    sum/count (correctly rounded); center_inc = increment sum / count with
+ *    the sum taken in a fixed order (deterministic; within ~1e-15 relative of
+ *    the exact mean); cx, cy as in jabba_dict.
+ *
+ *  len, inc: pieces, n_pieces[0] of them (device count, <= max_pieces)
+ *  alpha >= 0, scl >= 0 finite; B >= 1 pieces per block (a method parameter:
+ *  it changes results); symbols[max_pieces]: out.
+ *  dict: out; dict->capacity symbols.  Device status JABBA_ECAPACITY when k >
+ *  capacity (k is still written; only the first capacity centers are).
+ */
+int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces, double alpha,
+                   double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols, const jabba_dict *dict,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Nearest-center digitization against an existing dictionary (Sec. 3.2,
+ * c* = argmin_c ||p - c||, f_d = I_d(c*)): x = params[2]*(len/params[0]),
+ * y = inc/params[1], symbol = argmin_c (x - cx_c)^2 + (y - cy_c)^2 over all
+ * k symbols, ties to the lowest symbol.  symbols[max_pieces]: out.
+ */
+int jabba_encode(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                 const jabba_dict *dict, int32_t *symbols, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Inverse symbolization (Sec. 3.3).                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes for the reconstruct calls. */
+int jabba_reconstruct_workspace(int64_t n_series, size_t *bytes);
+
+/*
+ * Output sizes.  Quantization (Eq. repolygon) keeps the running sum of the
+ * integer lengths equal to the rounded running sum of the center lengths
+ * (halves away from zero); it is evaluated exactly in 128-bit fixed point at
+ * scale 2^52 (every center length >= 1 is a multiple of 2^-52).
+ * Series s gets 1 + sum(len^) points if it has pieces, otherwise
+ * min(n_s, 1) points.  out_off[n_series+1]: out (device); the total is
+ * out_off[n_series].
+ */
+int jabba_reconstruct_size(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off,
+                           int64_t n_series, const jabba_dict *dict, int64_t *out_off, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+/*
+ * Inverse digitization, quantization and inverse compression: V_0 = t0[s],
+ * V_j = V_{j-1} + center_inc (sequential per series), interior points
+ * V_{j-1} + (center_inc/len^_j)*q for 0 < q < len^_j, end point V_j.
+ * out[out_off[n_series]]: out.  lhat[max pieces]: optional out (may be NULL).
+ * values/series_off: optional originals; when values is non-NULL, sse[s] and
+ * cnt[s] receive the squared error over the first min(n_s, n^_s) points
+ * (Sec. 3.3, MSE = sum(sse)/sum(cnt)).
+ */
+int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off, int64_t n_series,
+                      const double *t0, const jabba_dict *dict, const int64_t *out_off, double *out, int64_t *lhat,
+                      const double *values, double *sse, int64_t *cnt, void *stream);
+
+/*
+ * Inverse compression straight from (len, inc) (Sec. 3.1: the polygonal
+ * chain is recovered from t_0 and the tuples).  out_off[n_series+1] is
+ * written (1 + sum(len) per series with pieces); same fill rule as above.
+ */
+int jabba_reconstruct_pieces(const int32_t *len, const double *inc, const int64_t *piece_off,
+                             const int64_t *series_off, int64_t n_series, const double *t0, int64_t *out_off,
+                             double *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Status.                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Synchronises `stream`, then copies the device status word of a workspace
+ * used by a previous call on that stream into *status (JABBA_OK or the first
+ * device-detected error code).  Returns JABBA_OK or JABBA_EHIP.
+ */
+int jabba_workspace_status(const void *workspace, void *stream, int32_t *status);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics.                                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * quot[i] = a[i] / b[i] and root[i] = sqrt(a[i]) evaluated with exactly the
+ * device code the library's kernels use for the scaling and the sort key
+ * (Sec. 3.2, Eq. tupseq2).  Lets a caller confirm that both are correctly
+ * rounded binary64 operations on the device at hand, which the bit-exact
+ * decisions rely on.  n >= 0 elements, device arrays.
+ */
+int jabba_fp64_selftest(const double *a, const double *b, double *quot, double *root, int64_t n, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched plan: the whole compress + digitize path captured once into a HIP  */
+/* graph (persistent compression kernel with a work queue ordered by domain   */
+/* length, every later kernel sized from upper bounds and device counters)   */
+/* and replayed with one graph launch per batch.                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct jabba_plan jabba_plan;
+
+typedef struct jabba_plan_desc {
+    /* inputs */
+    const double *values;
+    const int64_t *series_off;
+    int64_t n_series;
+    int64_t total_points;
+    int32_t D;
+    double tol;
+    int32_t max_len;
+    double alpha;
+    double scl;
+    int32_t B;
+    int64_t max_pieces; /* upper bound on the piece count, as given to jabba_digitize_workspace */
+    /* outputs (device) */
+    int32_t *len;
+    double *inc;
+    int64_t *piece_off;
+    int64_t *n_pieces;
+    int32_t *symbols;
+    jabba_dict dict;
+    /* workspaces (device) sized by the two workspace queries */
+    void *compress_ws;
+    size_t compress_ws_bytes;
+    void *digitize_ws;
+    size_t digitize_ws_bytes;
+    jabba_tuning tuning;
+} jabba_plan_desc;
+
+/*
+ * Captures the path for the buffers and sizes in *desc (they are bound to the
+ * plan) on an internal stream and instantiates the graph.  Synchronous.
+ */
+int jabba_plan_create(const jabba_plan_desc *desc, jabba_plan **plan);
+
+/* Replays the captured graph on `stream` (asynchronous). */
+int jabba_plan_run(jabba_plan *plan, void *stream);
+
+/* Frees the graph; buffers stay with the caller. */
+int jabba_plan_destroy(jabba_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JABBA_H */

@@ -1,0 +1,378 @@
+"""Python face of libjabba: compress / digitize / encode / reconstruct.
+
+Thin marshalling over the C ABI (include/jabba.h).  PyTorch is used only to
+hold device memory and to supply the current HIP stream; every step of the
+path runs in the library's HIP kernels.  There is no CPU fallback: on a
+machine without the built library or without a GPU these calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = [
+    "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "reconstruct",
+    "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer",
+]
+
+
+def _dev(device=None) -> torch.device:
+    if device is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    return torch.device(device)
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def tuning_struct(tuning: dict | None):
+    if not tuning:
+        return None
+    t = L.Tuning()
+    for k, v in tuning.items():
+        setattr(t, k, int(v))
+    return t
+
+
+def _tref(t):
+    return C.byref(t) if t is not None else None
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _as(t, dtype, device):
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    t = t.to(device=device, dtype=dtype)
+    return t.contiguous()
+
+
+def compress_workspace_bytes(n_series: int, total_points: int, D: int) -> int:
+    n = C.c_size_t()
+    L.check(L.lib().jabba_compress_workspace(n_series, total_points, D, C.byref(n)), "compress_workspace")
+    return n.value
+
+
+def digitize_workspace_bytes(max_pieces: int, B: int) -> int:
+    n = C.c_size_t()
+    L.check(L.lib().jabba_digitize_workspace(max_pieces, B, C.byref(n)), "digitize_workspace")
+    return n.value
+
+
+def recon_workspace_bytes(n_series: int) -> int:
+    n = C.c_size_t()
+    L.check(L.lib().jabba_reconstruct_workspace(n_series, C.byref(n)), "reconstruct_workspace")
+    return n.value
+
+
+@dataclass
+class Pieces:
+    """Compressed pieces on the device (capacity max_pieces, live count in n_pieces)."""
+    len: torch.Tensor        # int32[max_pieces]
+    inc: torch.Tensor        # float64[max_pieces]
+    piece_off: torch.Tensor  # int64[n_series + 1]
+    n_pieces: torch.Tensor   # int64[1]
+    max_pieces: int
+    workspace: torch.Tensor | None = None
+
+    def count(self) -> int:
+        return int(self.n_pieces.item())
+
+    def host(self):
+        n = self.count()
+        return (self.len[:n].cpu().numpy(), self.inc[:n].cpu().numpy(), self.piece_off.cpu().numpy())
+
+
+class Dictionary:
+    """Symbolic centers (jabba_dict) in caller-owned device memory."""
+
+    def __init__(self, capacity: int, device=None):
+        dev = _dev(device)
+        cap = max(int(capacity), 1)
+        self.capacity = cap
+        self.params = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.k = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.center_len = torch.zeros(cap, dtype=torch.float64, device=dev)
+        self.center_inc = torch.zeros(cap, dtype=torch.float64, device=dev)
+        self.cx = torch.zeros(cap, dtype=torch.float64, device=dev)
+        self.cy = torch.zeros(cap, dtype=torch.float64, device=dev)
+        self.count = torch.zeros(cap, dtype=torch.int64, device=dev)
+
+    def struct(self) -> L.Dict:
+        return L.Dict(self.capacity, self.params.data_ptr(), self.k.data_ptr(), self.center_len.data_ptr(),
+                      self.center_inc.data_ptr(), self.cx.data_ptr(), self.cy.data_ptr(), self.count.data_ptr())
+
+    def size(self) -> int:
+        return int(self.k.item())
+
+    def host(self) -> dict:
+        k = min(self.size(), self.capacity)
+        p = self.params.cpu().numpy()
+        return {"k": self.size(), "sigma_len": float(p[0]), "sigma_inc": float(p[1]), "scl": float(p[2]),
+                "alpha": float(p[3]), "center_len": self.center_len[:k].cpu().numpy(),
+                "center_inc": self.center_inc[:k].cpu().numpy(), "cx": self.cx[:k].cpu().numpy(),
+                "cy": self.cy[:k].cpu().numpy(), "count": self.count[:k].cpu().numpy()}
+
+    @classmethod
+    def from_host(cls, sigma_len, sigma_inc, scl, alpha, center_len, center_inc, cx, cy, count=None, device=None):
+        """Upload a dictionary (for example a saved one) to the device."""
+        k = len(center_len)
+        d = cls(max(k, 1), device)
+        dev = d.params.device
+        d.params.copy_(torch.tensor([sigma_len, sigma_inc, scl, alpha], dtype=torch.float64))
+        d.k.fill_(k)
+        if k:
+            d.center_len[:k].copy_(_as(center_len, torch.float64, dev))
+            d.center_inc[:k].copy_(_as(center_inc, torch.float64, dev))
+            d.cx[:k].copy_(_as(cx, torch.float64, dev))
+            d.cy[:k].copy_(_as(cy, torch.float64, dev))
+            if count is not None:
+                d.count[:k].copy_(_as(count, torch.int64, dev))
+        return d
+
+    def save(self, path: str) -> None:
+        h = self.host()
+        np.savez(path, **{k: np.asarray(v) for k, v in h.items()})
+
+    @classmethod
+    def load(cls, path: str, device=None):
+        z = np.load(path, allow_pickle=False)
+        return cls.from_host(float(z["sigma_len"]), float(z["sigma_inc"]), float(z["scl"]), float(z["alpha"]),
+                             z["center_len"], z["center_inc"], z["cx"], z["cy"], z["count"], device)
+
+
+def workspace_status(ws: torch.Tensor, stream=None) -> int:
+    st = C.c_int32()
+    L.check(L.lib().jabba_workspace_status(_p(ws), _stream(stream), C.byref(st)), "workspace_status")
+    return st.value
+
+
+def compress(values: torch.Tensor, series_off: torch.Tensor, D: int, tol: float, max_len: int = 0,
+             tuning: dict | None = None, max_pieces: int | None = None, out: Pieces | None = None,
+             workspace: torch.Tensor | None = None, stream=None) -> Pieces:
+    """Phase I + II of Alg. 1 on the device (see jabba_compress)."""
+    dev = values.device
+    n_series = series_off.numel() - 1
+    total = values.numel()
+    cap = int(max_pieces) if max_pieces is not None else max(total, 1)
+    if out is None:
+        out = Pieces(torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                     torch.empty(max(cap, 1), dtype=torch.float64, device=dev),
+                     torch.empty(n_series + 1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int64, device=dev), cap)
+    if workspace is None:
+        workspace = _ws(compress_workspace_bytes(n_series, total, D), dev)
+    out.workspace = workspace
+    t = tuning_struct(tuning)
+    rc = L.lib().jabba_compress(_p(values), _p(series_off), n_series, total, int(D), float(tol), int(max_len),
+                                _tref(t), _p(out.len), _p(out.inc), _p(out.piece_off), _p(out.n_pieces),
+                                _p(workspace), workspace.numel(), _stream(stream))
+    L.check(rc, "jabba_compress")
+    return out
+
+
+def compress_plain(values: torch.Tensor, series_off: torch.Tensor, series_off_host: np.ndarray, D: int, tol: float,
+                   max_len: int = 0, out: Pieces | None = None, workspace: torch.Tensor | None = None,
+                   stream=None) -> Pieces:
+    """One launch per series (the per-domain-launch baseline); same outputs as compress."""
+    dev = values.device
+    so_h = np.ascontiguousarray(series_off_host, dtype=np.int64)
+    n_series = so_h.size - 1
+    total = int(so_h[-1]) if so_h.size else 0
+    cap = max(total, 1)
+    if out is None:
+        out = Pieces(torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.float64, device=dev),
+                     torch.empty(n_series + 1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int64, device=dev), cap)
+    if workspace is None:
+        workspace = _ws(compress_workspace_bytes(n_series, total, D), dev)
+    out.workspace = workspace
+    rc = L.lib().jabba_compress_plain(_p(values), _p(series_off), so_h.ctypes.data_as(C.c_void_p), n_series, int(D),
+                                      float(tol), int(max_len), _p(out.len), _p(out.inc), _p(out.piece_off),
+                                      _p(out.n_pieces), _p(workspace), workspace.numel(), _stream(stream))
+    L.check(rc, "jabba_compress_plain")
+    return out
+
+
+def digitize(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, alpha: float,
+             scl: float = 1.0, B: int = 4096, capacity: int | None = None, tuning: dict | None = None,
+             symbols: torch.Tensor | None = None, dictionary: Dictionary | None = None,
+             workspace: torch.Tensor | None = None, stream=None):
+    """Phase III of Alg. 1 (two-stage digitization).  Returns (symbols, Dictionary, workspace)."""
+    dev = length.device
+    if symbols is None:
+        symbols = torch.empty(max(max_pieces, 1), dtype=torch.int32, device=dev)
+    if dictionary is None:
+        dictionary = Dictionary(capacity if capacity is not None else max(max_pieces, 1), dev)
+    if workspace is None:
+        workspace = _ws(digitize_workspace_bytes(max_pieces, B), dev)
+    d = dictionary.struct()
+    t = tuning_struct(tuning)
+    rc = L.lib().jabba_digitize(_p(length), _p(inc), _p(n_pieces), int(max_pieces), float(alpha), float(scl), int(B),
+                                _tref(t), _p(symbols), C.byref(d), _p(workspace), workspace.numel(), _stream(stream))
+    L.check(rc, "jabba_digitize")
+    return symbols, dictionary, workspace
+
+
+def encode(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, dictionary: Dictionary,
+           symbols: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Nearest-center symbols against a resident dictionary (see jabba_encode)."""
+    if symbols is None:
+        symbols = torch.empty(max(max_pieces, 1), dtype=torch.int32, device=length.device)
+    d = dictionary.struct()
+    rc = L.lib().jabba_encode(_p(length), _p(inc), _p(n_pieces), int(max_pieces), C.byref(d), _p(symbols),
+                              _stream(stream))
+    L.check(rc, "jabba_encode")
+    return symbols
+
+
+def reconstruct(symbols: torch.Tensor, piece_off: torch.Tensor, series_off: torch.Tensor, t0: torch.Tensor,
+                dictionary: Dictionary, values: torch.Tensor | None = None, want_lhat: bool = False, stream=None):
+    """Inverse symbolization.  Returns dict(out, out_off, lhat, sse, cnt, status); synchronises once for the size."""
+    dev = symbols.device
+    ns = piece_off.numel() - 1
+    ws = _ws(recon_workspace_bytes(ns), dev)
+    out_off = torch.empty(ns + 1, dtype=torch.int64, device=dev)
+    d = dictionary.struct()
+    st = _stream(stream)
+    L.check(L.lib().jabba_reconstruct_size(_p(symbols), _p(piece_off), _p(series_off), ns, C.byref(d), _p(out_off),
+                                           _p(ws), ws.numel(), st), "jabba_reconstruct_size")
+    status = workspace_status(ws, stream)
+    total = int(out_off[-1].item())
+    out = torch.empty(max(total, 1), dtype=torch.float64, device=dev)
+    lhat = torch.empty(max(symbols.numel(), 1), dtype=torch.int64, device=dev) if want_lhat else None
+    sse = cnt = None
+    if values is not None:
+        sse = torch.empty(max(ns, 1), dtype=torch.float64, device=dev)
+        cnt = torch.empty(max(ns, 1), dtype=torch.int64, device=dev)
+    L.check(L.lib().jabba_reconstruct(_p(symbols), _p(piece_off), _p(series_off), ns, _p(t0), C.byref(d),
+                                      _p(out_off), _p(out), _p(lhat), _p(values), _p(sse), _p(cnt), st),
+            "jabba_reconstruct")
+    return {"out": out[:total], "out_off": out_off, "lhat": lhat, "sse": sse, "cnt": cnt, "status": status}
+
+
+def reconstruct_pieces(length: torch.Tensor, inc: torch.Tensor, piece_off: torch.Tensor, series_off: torch.Tensor,
+                       t0: torch.Tensor, total_out: int | None = None, stream=None):
+    """Polyline straight from the pieces.  Returns (out, out_off)."""
+    dev = length.device
+    ns = piece_off.numel() - 1
+    ws = _ws(recon_workspace_bytes(ns), dev)
+    out_off = torch.empty(ns + 1, dtype=torch.int64, device=dev)
+    cap = total_out if total_out is not None else None
+    if cap is None:
+        # every series has 1 + sum(len) <= its point count points
+        cap = int(series_off[-1].item()) if series_off.numel() else 0
+    out = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    L.check(L.lib().jabba_reconstruct_pieces(_p(length), _p(inc), _p(piece_off), _p(series_off), ns, _p(t0),
+                                             _p(out_off), _p(out), _p(ws), ws.numel(), _stream(stream)),
+            "jabba_reconstruct_pieces")
+    return out, out_off
+
+
+class Plan:
+    """Compress + digitize captured once into a HIP graph; run() replays it."""
+
+    def __init__(self, values: torch.Tensor, series_off: torch.Tensor, D: int, tol: float, alpha: float,
+                 scl: float = 1.0, B: int = 4096, max_len: int = 0, max_pieces: int | None = None,
+                 capacity: int | None = None, tuning: dict | None = None):
+        dev = values.device
+        self.n_series = series_off.numel() - 1
+        self.total = values.numel()
+        self.max_pieces = int(max_pieces) if max_pieces is not None else max(self.total, 1)
+        mp = self.max_pieces
+        self.values, self.series_off = values, series_off
+        self.pieces = Pieces(torch.empty(mp, dtype=torch.int32, device=dev),
+                             torch.empty(mp, dtype=torch.float64, device=dev),
+                             torch.empty(self.n_series + 1, dtype=torch.int64, device=dev),
+                             torch.empty(1, dtype=torch.int64, device=dev), mp)
+        self.symbols = torch.empty(mp, dtype=torch.int32, device=dev)
+        self.dictionary = Dictionary(capacity if capacity is not None else mp, dev)
+        self.cws = _ws(compress_workspace_bytes(self.n_series, self.total, D), dev)
+        self.dws = _ws(digitize_workspace_bytes(mp, B), dev)
+        desc = L.PlanDesc()
+        desc.values, desc.series_off = values.data_ptr(), series_off.data_ptr()
+        desc.n_series, desc.total_points, desc.D, desc.tol = self.n_series, self.total, int(D), float(tol)
+        desc.max_len, desc.alpha, desc.scl, desc.B, desc.max_pieces = int(max_len), float(alpha), float(scl), int(B), mp
+        desc.len, desc.inc = self.pieces.len.data_ptr(), self.pieces.inc.data_ptr()
+        desc.piece_off, desc.n_pieces = self.pieces.piece_off.data_ptr(), self.pieces.n_pieces.data_ptr()
+        desc.symbols = self.symbols.data_ptr()
+        desc.dict = self.dictionary.struct()
+        desc.compress_ws, desc.compress_ws_bytes = self.cws.data_ptr(), self.cws.numel()
+        desc.digitize_ws, desc.digitize_ws_bytes = self.dws.data_ptr(), self.dws.numel()
+        t = tuning_struct(tuning)
+        if t is not None:
+            desc.tuning = t
+        torch.cuda.synchronize(dev)
+        h = C.c_void_p()
+        L.check(L.lib().jabba_plan_create(C.byref(desc), C.byref(h)), "jabba_plan_create")
+        self._h = h
+
+    def run(self, stream=None) -> None:
+        L.check(L.lib().jabba_plan_run(self._h, _stream(stream)), "jabba_plan_run")
+
+    def status(self) -> tuple[int, int]:
+        return workspace_status(self.cws), workspace_status(self.dws)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            L.lib().jabba_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Symbolizer:
+    """Preallocated compress + digitize for one workload shape (eager launches).
+
+    Buffers and workspaces are allocated once; run() only enqueues kernels.
+    """
+
+    def __init__(self, n_series: int, total_points: int, D: int, tol: float, alpha: float, scl: float = 1.0,
+                 B: int = 4096, max_len: int = 0, max_pieces: int | None = None, capacity: int | None = None,
+                 tuning: dict | None = None, device=None):
+        dev = _dev(device)
+        self.D, self.tol, self.alpha, self.scl, self.B, self.max_len = D, tol, alpha, scl, B, max_len
+        self.tuning = tuning
+        mp = int(max_pieces) if max_pieces is not None else max(total_points, 1)
+        self.max_pieces = mp
+        self.pieces = Pieces(torch.empty(mp, dtype=torch.int32, device=dev),
+                             torch.empty(mp, dtype=torch.float64, device=dev),
+                             torch.empty(n_series + 1, dtype=torch.int64, device=dev),
+                             torch.empty(1, dtype=torch.int64, device=dev), mp)
+        self.symbols = torch.empty(mp, dtype=torch.int32, device=dev)
+        self.dictionary = Dictionary(capacity if capacity is not None else mp, dev)
+        self.cws = _ws(compress_workspace_bytes(n_series, total_points, D), dev)
+        self.dws = _ws(digitize_workspace_bytes(mp, B), dev)
+
+    def compress(self, values, series_off, stream=None) -> Pieces:
+        return compress(values, series_off, self.D, self.tol, self.max_len, self.tuning, self.max_pieces,
+                        out=self.pieces, workspace=self.cws, stream=stream)
+
+    def digitize(self, stream=None):
+        p = self.pieces
+        return digitize(p.len, p.inc, p.n_pieces, self.max_pieces, self.alpha, self.scl, self.B, tuning=self.tuning,
+                        symbols=self.symbols, dictionary=self.dictionary, workspace=self.dws, stream=stream)
+
+    def run(self, values, series_off, stream=None):
+        self.compress(values, series_off, stream)
+        return self.digitize(stream)
+
+    def status(self) -> tuple[int, int]:
+        return workspace_status(self.cws), workspace_status(self.dws)

@@ -1,0 +1,141 @@
+// Internal helpers shared by the HIP sources of libjabba (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "jabba.h"
+
+namespace jabba {
+
+constexpr int kWave = 64;
+
+// Device status bits (OR-ed into the first word of a workspace).
+enum : int32_t {
+    kStNonFinite = 1,
+    kStCapacity = 2,
+    kStOverflow = 4,
+    kStInvalid = 8,
+};
+
+// ---------------------------------------------------------------- host side
+#define JB_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return JABBA_EHIP;       \
+    } while (0)
+
+#define JB_LAUNCH_CHECK()                               \
+    do {                                                \
+        hipError_t e_ = hipGetLastError();              \
+        if (e_ != hipSuccess) return JABBA_EHIP;        \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Carves typed sub-buffers out of one caller-provided workspace.  The same
+// sequence of take() calls is used for the size query and for the call, so
+// offsets always agree.
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b = nullptr) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t n) {
+        off = align_up(off, 256);
+        T *p = reinterpret_cast<T *>(base + off);
+        off += (n ? n : 1) * sizeof(T);
+        return base ? p : nullptr;
+    }
+    size_t bytes() const { return align_up(off, 256); }
+};
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+// ---------------------------------------------------------------- device side
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int ffs64(uint64_t m) { return m ? __builtin_ctzll(m) : -1; }
+
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src); }
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) { return __shfl(v, src); }
+__device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src); }
+
+// Sum of a wavefront's values as a balanced pairwise tree over lanes
+// (lane pairs (0,1), (2,3), ..., then pairs of pairs).  Floating-point
+// addition is commutative, so every lane ends with the same bits.
+__device__ __forceinline__ double wave_tree_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+__device__ __forceinline__ void set_status(int32_t *st, int32_t bit) {
+    if (st) atomicOr(st, bit);
+}
+
+// Scaled coordinates of a piece (Eq. tupseq2); every kernel that needs x, y
+// or the key evaluates them with this one function so the bits agree.
+struct Scaled {
+    double x, y;
+};
+__device__ __forceinline__ Scaled scale_piece(int32_t len, double inc, double scl, double sl, double si) {
+    Scaled s;
+    double q = (double)len / sl;
+    s.x = scl * q;
+    s.y = inc / si;
+    return s;
+}
+__device__ __forceinline__ double piece_key(Scaled s) {
+    double xx = s.x * s.x;
+    double yy = s.y * s.y;
+    return __dsqrt_rn(xx + yy);
+}
+
+// ---------------------------------------------------------------- launchers
+// scan.hip: exclusive scans (out[0..n] with out[n] = total), n read on device
+// when n_dev != nullptr (clamped to n_max), otherwise n = n_max.
+size_t scan_workspace(int64_t n_max);
+int scan_i32_to_i64(const int32_t *in, int64_t *out, const int64_t *n_dev, int64_t n_max, void *ws, hipStream_t st);
+int scan_i64_to_i64(const int64_t *in, int64_t *out, const int64_t *n_dev, int64_t n_max, void *ws, hipStream_t st);
+int scan_u32_to_u32(const uint32_t *in, uint32_t *out, const int64_t *n_dev, int64_t n_max, void *ws,
+                    hipStream_t st);
+
+// fill kernels (graph-safe replacements for memset)
+int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
+
+// sort.hip: stable LSD radix sort of (u64 key, u32 value) pairs.
+struct SortBuffers {
+    uint64_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;      // 256 * n_tiles_max
+    uint32_t *ghist;     // 8 * 256
+    int32_t *ctl;        // [0] = current buffer, [1..8] = skip flags
+    void *scan_ws;
+};
+size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b);
+// Resets the control words and the global digit histograms.
+int radix_sort_init(const SortBuffers &b, hipStream_t st);
+// Global histograms of the eight digits of keys[0] (after the keys are written).
+int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);
+// Sorts n (device count) pairs held in keys[0]/vals[0]; the result is in
+// keys[ctl[0]], vals[ctl[0]] (read on device by consumers).
+int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);
+
+}  // namespace jabba

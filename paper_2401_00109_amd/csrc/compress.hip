@@ -1,0 +1,476 @@
+// Phase I (domain construction) and Phase II (parallel compression) of
+// Alg. 1, with the greedy ABBA compression of Sec. 3.1 (Eq. compress).
+//
+// Layout in HBM
+//   values  f64[total_points]                 (input, series concatenated)
+//   doms    {start i64, nint i32, series i32}  one per domain, canonical order
+//   queue   i32[n_dom]                         domain ids, longest first
+//   staging len i32 / inc f64 indexed by the domain's first point: domain d
+//           writes its pieces at [start_d, start_d + count_d); since
+//           count_d <= nint_d = start_{d+1} - start_d the regions never overlap
+//   output  len i32[N], inc f64[N]             canonical (series, domain, position)
+//
+// compress_kernel: W lanes test W consecutive candidate end points of one
+// domain together (W = 64: one wavefront per domain, the form that tests 64
+// candidates per round; W = 1: every lane grows its own domain).  Each lane
+// accumulates its candidate's squared error in ascending k exactly as the
+// sequential definition does, so the decision bits are identical for every W.
+// A round is decided as soon as the smallest failing candidate has finished
+// its sum and every smaller candidate has finished too (early exit); a ballot
+// over the group finds that candidate.  Groups pull the next domain from an
+// atomic work queue ordered by domain length (longest first), so the launch
+// is persistent and balances uneven series.
+#include "common.h"
+
+namespace jabba {
+
+struct Dom {
+    int64_t start;
+    int32_t nint;
+    int32_t series;
+};
+
+namespace {
+
+__global__ void k_series_domains(const int64_t *__restrict__ series_off, int64_t n_series, int32_t D,
+                                 int32_t *__restrict__ ndom, int32_t *status) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_series) return;
+    int64_t n = series_off[s + 1] - series_off[s];
+    if (n < 0) {
+        set_status(status, kStOverflow);
+        n = 0;
+    }
+    ndom[s] = n >= 2 ? (int32_t)((n - 1 + D - 1) / D) : 0;
+}
+
+__global__ void k_fill_domains(const int64_t *__restrict__ series_off, const int64_t *__restrict__ dom_off,
+                               int64_t n_series, int32_t D, Dom *__restrict__ doms,
+                               unsigned long long *__restrict__ len_hist) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_series) return;
+    int64_t lo = series_off[s], n = series_off[s + 1] - series_off[s];
+    int64_t d0 = dom_off[s];
+    int64_t d = 0;
+    for (int64_t a = 0; a + 1 < n; a += D, ++d) {
+        int64_t b = a + D < n - 1 ? a + D : n - 1;
+        Dom x;
+        x.start = lo + a;
+        x.nint = (int32_t)(b - a);
+        x.series = (int32_t)s;
+        doms[d0 + d] = x;
+        if (len_hist) atomicAdd(&len_hist[D - x.nint], 1ull);
+    }
+}
+
+// queue position by descending length (counting sort; order inside a bin is
+// irrelevant to the results)
+__global__ void k_queue_scatter(const Dom *__restrict__ doms, const int64_t *__restrict__ n_dom_p, int64_t max_dom,
+                                int32_t D, unsigned long long *__restrict__ cursor, int32_t *__restrict__ queue) {
+    int64_t n_dom = *n_dom_p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_dom && i < max_dom;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long p = atomicAdd(&cursor[D - doms[i].nint], 1ull);
+        queue[p] = (int32_t)i;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void k_prepare(int32_t *status, int32_t *q_head) {
+    if (threadIdx.x == 0) {
+        status[0] = 0;
+        *q_head = 0;
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t, const Dom *__restrict__ doms,
+                                                   const int32_t *__restrict__ queue,
+                                                   const int64_t *__restrict__ n_dom_p, int32_t *__restrict__ q_head,
+                                                   int64_t direct_base, int64_t direct_end, double tol2,
+                                                   int32_t max_len, int32_t *__restrict__ st_len,
+                                                   double *__restrict__ st_inc, int32_t *__restrict__ dom_count,
+                                                   int32_t *status) {
+    const int lane = lane_id();
+    const int j = lane & (W - 1);
+    const int leader = lane - j;
+    const uint64_t gmask = (W == 64) ? ~0ull : (((1ull << W) - 1ull) << leader);
+    const int64_t n_dom = *n_dom_p;
+    const bool direct = direct_base >= 0;
+    const int64_t wave_g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+
+    // group state, replicated over the group's lanes
+    int32_t dom = -1;
+    bool exhausted = false;
+    int64_t s = 0, e = 0, obase = 0;
+    int32_t np = 0;
+    double ts = 0.0;
+    int32_t c0 = 2;
+    int32_t k = 1;
+    // lane state: candidate length c of this lane in the current round
+    int32_t c = 0;
+    bool valid = false;
+    double slope = 0.0, acc = 0.0, thr = 0.0;
+    bool setup = false;
+
+    if (direct) {
+        // one domain per group, no queue
+        int64_t d = direct_base + wave_g * (kWave / W) + lane / W;
+        exhausted = true;
+        if (d < direct_end) {
+            dom = (int32_t)d;
+            Dom x = doms[dom];
+            s = x.start;
+            e = x.start + x.nint;
+            obase = x.start;
+            np = 0;
+            ts = t[s];
+            if (j == 0 && !isfinite(ts)) set_status(status, kStNonFinite);
+            c0 = 2;
+            setup = true;
+        }
+    }
+
+    for (;;) {
+        if (!direct) {
+            const bool need = (j == 0) && dom < 0 && !exhausted;
+            const uint64_t nm = ballot(need);
+            if (nm) {
+                const int first = ffs64(nm);
+                int base = 0;
+                if (lane == first) base = atomicAdd(q_head, (int)__popcll(nm));
+                base = shfl_i(base, first);
+                int got = dom;
+                bool ex = exhausted;
+                if (need) {
+                    int64_t qp = (int64_t)base + __popcll(nm & lanemask_lt());
+                    if (qp < n_dom)
+                        got = queue[qp];
+                    else
+                        ex = true;
+                }
+                got = shfl_i(got, leader);
+                ex = shfl_i((int)ex, leader) != 0;
+                if (got >= 0 && dom < 0) {
+                    dom = got;
+                    Dom x = doms[dom];
+                    s = x.start;
+                    e = x.start + x.nint;
+                    obase = x.start;
+                    np = 0;
+                    ts = t[s];
+                    if (j == 0 && !isfinite(ts)) set_status(status, kStNonFinite);
+                    c0 = 2;
+                    setup = true;
+                }
+                exhausted = ex;
+            }
+        }
+        if (setup) {
+            c = c0 + j;
+            valid = (s + c <= e) && (max_len <= 0 || c <= max_len);
+            if (valid) {
+                const double te = t[s + c];
+                slope = (te - ts) / (double)c;
+                thr = (double)(c - 1) * tol2;
+            }
+            acc = 0.0;
+            k = 1;
+            setup = false;
+        }
+        const bool act = dom >= 0;
+        if (ballot(act || !exhausted) == 0ull) break;
+
+        // one interior term of this lane's candidate
+        if (act && valid && k < c) {
+            double v = slope * (double)k;
+            v = ts + v;
+            const double r = v - t[s + k];
+            acc = acc + r * r;
+        }
+        if (act) ++k;
+
+        // verdicts: a lane's candidate is known once all its c-1 terms are in
+        const bool fail = act && (!valid || (c <= k && !(acc <= thr)));
+        const bool done = act && (!valid || c <= k);
+        const uint64_t fm = ballot(fail) & gmask;
+        const uint64_t dm = ballot(done) & gmask;
+        if (!act) continue;
+        const int f = fm ? (ffs64(fm) - leader) : -1;  // first failing candidate in the group
+        if (f >= 0 && c0 + f - 1 <= k) {
+            // every smaller candidate has finished and passed: piece length is
+            // the last accepted candidate
+            const int32_t L = c0 + f - 1;
+            const double tend = t[s + L];
+            if (j == 0) {
+                if (!isfinite(tend)) set_status(status, kStNonFinite);
+                st_len[obase + np] = L;
+                st_inc[obase + np] = tend - ts;
+            }
+            ++np;
+            s += L;
+            ts = tend;
+            if (s >= e) {
+                if (j == 0) dom_count[dom] = np;
+                dom = -1;
+            } else {
+                c0 = 2;
+                setup = true;
+            }
+        } else if (fm == 0ull && dm == gmask) {
+            // all W candidates accepted: next round
+            c0 += W;
+            setup = true;
+        }
+    }
+}
+
+__global__ void k_compact(const Dom *__restrict__ doms, const int64_t *__restrict__ n_dom_p,
+                          const int32_t *__restrict__ dom_count, const int64_t *__restrict__ dom_poff,
+                          const int32_t *__restrict__ st_len, const double *__restrict__ st_inc,
+                          int32_t *__restrict__ len, double *__restrict__ inc) {
+    const int64_t n_dom = *n_dom_p;
+    const int lane = lane_id();
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t d = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; d < n_dom; d += waves) {
+        const int64_t src = doms[d].start;
+        const int64_t dst = dom_poff[d];
+        const int32_t cnt = dom_count[d];
+        for (int32_t i = lane; i < cnt; i += kWave) {
+            len[dst + i] = st_len[src + i];
+            inc[dst + i] = st_inc[src + i];
+        }
+    }
+}
+
+__global__ void k_piece_off(const int64_t *__restrict__ dom_off, const int64_t *__restrict__ dom_poff,
+                            int64_t n_series, int64_t *__restrict__ piece_off, int64_t *__restrict__ n_pieces) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_series) return;
+    int64_t v = dom_poff[dom_off[s]];
+    piece_off[s] = v;
+    if (s == n_series) *n_pieces = v;
+}
+
+struct CompressWs {
+    int32_t *status;
+    int32_t *q_head;
+    int32_t *ndom;
+    int64_t *dom_off;
+    Dom *doms;
+    unsigned long long *len_hist;
+    int64_t *bin_off;
+    int32_t *queue;
+    int32_t *dom_count;
+    int64_t *dom_poff;
+    int32_t *st_len;
+    double *st_inc;
+    void *scan_ws;
+    size_t bytes;
+};
+
+int64_t max_domains(int64_t n_series, int64_t total_points, int32_t D) {
+    return total_points / D + n_series + 1;
+}
+
+CompressWs carve_compress(void *ws, int64_t n_series, int64_t total_points, int32_t D) {
+    const int64_t md = max_domains(n_series, total_points, D);
+    Carve c(ws);
+    CompressWs w;
+    w.status = c.take<int32_t>(64);
+    w.q_head = c.take<int32_t>(64);
+    w.ndom = c.take<int32_t>(n_series + 1);
+    w.dom_off = c.take<int64_t>(n_series + 2);
+    w.doms = c.take<Dom>(md);
+    w.len_hist = c.take<unsigned long long>((size_t)D + 2);
+    w.bin_off = c.take<int64_t>((size_t)D + 3);
+    w.queue = c.take<int32_t>(md);
+    w.dom_count = c.take<int32_t>(md);
+    w.dom_poff = c.take<int64_t>(md + 1);
+    w.st_len = c.take<int32_t>(total_points);
+    w.st_inc = c.take<double>(total_points);
+    int64_t scan_n = md > n_series + 1 ? md : n_series + 1;
+    if (scan_n < D + 2) scan_n = D + 2;
+    w.scan_ws = c.take<char>(scan_workspace(scan_n));
+    w.bytes = c.bytes();
+    return w;
+}
+
+int validate(const double *values, const int64_t *series_off, int64_t n_series, int64_t total_points, int32_t D,
+             double tol, int32_t max_len, int32_t *len, double *inc, int64_t *piece_off, int64_t *n_pieces) {
+    if (n_series < 0 || total_points < 0 || D < 1 || max_len < 0) return JABBA_EINVAL;
+    if (!(tol >= 0.0) || !(tol <= 1.0e150)) return JABBA_EINVAL;
+    if (total_points - n_series >= (int64_t)1 << 31) return JABBA_EOVERFLOW;
+    if (max_domains(n_series, total_points, D) >= ((int64_t)1 << 31) - 65536) return JABBA_EOVERFLOW;
+    if (!series_off || !piece_off || !n_pieces) return JABBA_EINVAL;
+    if (total_points > 0 && (!values || !len || !inc)) return JABBA_EINVAL;
+    return JABBA_OK;
+}
+
+int domain_table(const CompressWs &w, const int64_t *series_off, int64_t n_series, int64_t total_points, int32_t D,
+                 bool want_queue, hipStream_t st) {
+    const int64_t md = max_domains(n_series, total_points, D);
+    const unsigned sb = (unsigned)((n_series + 255) / 256 > 0 ? (n_series + 255) / 256 : 1);
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(64), 0, st, w.status, w.q_head);
+    JB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_series_domains, dim3(sb), dim3(256), 0, st, series_off, n_series, D, w.ndom, w.status);
+    JB_LAUNCH_CHECK();
+    int rc = scan_i32_to_i64(w.ndom, w.dom_off, nullptr, n_series, w.scan_ws, st);
+    if (rc) return rc;
+    if (want_queue) {
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((D + 2 + 255) / 256)), dim3(256), 0, st, w.len_hist,
+                           (int64_t)D + 2);
+        JB_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_fill_domains, dim3(sb), dim3(256), 0, st, series_off, w.dom_off, n_series, D, w.doms,
+                       want_queue ? w.len_hist : nullptr);
+    JB_LAUNCH_CHECK();
+    if (want_queue) {
+        rc = scan_i64_to_i64(reinterpret_cast<const int64_t *>(w.len_hist), w.bin_off, nullptr, (int64_t)D + 1,
+                             w.scan_ws, st);
+        if (rc) return rc;
+        int64_t blocks = (md + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_queue_scatter, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, w.dom_off + n_series,
+                           md, D, reinterpret_cast<unsigned long long *>(w.bin_off), w.queue);
+        JB_LAUNCH_CHECK();
+    }
+    return JABBA_OK;
+}
+
+int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t D, int32_t *len, double *inc,
+           int64_t *piece_off, int64_t *n_pieces, hipStream_t st) {
+    const int64_t md = max_domains(n_series, total_points, D);
+    const int64_t *n_dom_p = w.dom_off + n_series;
+    int rc = scan_i32_to_i64(w.dom_count, w.dom_poff, n_dom_p, md, w.scan_ws, st);
+    if (rc) return rc;
+    int64_t blocks = (md * kWave + 255) / 256;
+    int cap = device_cu_count() * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, n_dom_p, w.dom_count, w.dom_poff,
+                       w.st_len, w.st_inc, len, inc);
+    JB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_piece_off, dim3((unsigned)((n_series + 1 + 255) / 256)), dim3(256), 0, st, w.dom_off,
+                       w.dom_poff, n_series, piece_off, n_pieces);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
+
+template <int W>
+void launch_w(dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
+              int64_t dbase, int64_t dend, double tol2, int32_t max_len) {
+    hipLaunchKernelGGL((k_compress<W>), g, b, 0, st, t, w.doms, w.queue, n_dom_p, w.q_head, dbase, dend, tol2,
+                       max_len, w.st_len, w.st_inc, w.dom_count, w.status);
+}
+
+int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
+                    const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len) {
+    switch (W) {
+        case 1: launch_w<1>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 2: launch_w<2>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 4: launch_w<4>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 8: launch_w<8>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 16: launch_w<16>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 32: launch_w<32>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 64: launch_w<64>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        default: return JABBA_EINVAL;
+    }
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
+
+}  // namespace
+
+// defaults (the autotuner may pick others; results never change)
+constexpr int kDefaultW = 4;
+constexpr int kDefaultWavesPerBlock = 4;
+constexpr int kDefaultBlocksPerCu = 8;
+
+}  // namespace jabba
+
+using namespace jabba;
+
+extern "C" int jabba_compress_workspace(int64_t n_series, int64_t total_points, int32_t D, size_t *bytes) {
+    if (!bytes || n_series < 0 || total_points < 0 || D < 1) return JABBA_EINVAL;
+    *bytes = carve_compress(nullptr, n_series, total_points, D).bytes;
+    return JABBA_OK;
+}
+
+extern "C" int jabba_compress(const double *values, const int64_t *series_off, int64_t n_series, int64_t total_points,
+                              int32_t D, double tol, int32_t max_len, const jabba_tuning *tuning, int32_t *len,
+                              double *inc, int64_t *piece_off, int64_t *n_pieces, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+    int rc = validate(values, series_off, n_series, total_points, D, tol, max_len, len, inc, piece_off, n_pieces);
+    if (rc) return rc;
+    CompressWs w0 = carve_compress(nullptr, n_series, total_points, D);
+    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    CompressWs w = carve_compress(workspace, n_series, total_points, D);
+    hipStream_t st = (hipStream_t)stream;
+    int W = kDefaultW, wpb = kDefaultWavesPerBlock, bpc = kDefaultBlocksPerCu;
+    if (tuning) {
+        if (tuning->lanes_per_domain) W = tuning->lanes_per_domain;
+        if (tuning->waves_per_block) wpb = tuning->waves_per_block;
+        if (tuning->blocks_per_cu) bpc = tuning->blocks_per_cu;
+    }
+    if (wpb < 1 || wpb > 16 || bpc < 1 || bpc > 32) return JABBA_EINVAL;
+    if (W != 1 && W != 2 && W != 4 && W != 8 && W != 16 && W != 32 && W != 64) return JABBA_EINVAL;
+    rc = domain_table(w, series_off, n_series, total_points, D, true, st);
+    if (rc) return rc;
+    const int64_t *n_dom_p = w.dom_off + n_series;
+    dim3 grid((unsigned)(device_cu_count() * bpc)), block((unsigned)(wpb * kWave));
+    rc = launch_compress(W, grid, block, st, values, w, n_dom_p, -1, 0, tol * tol, max_len);
+    if (rc) return rc;
+    return finish(w, n_series, total_points, D, len, inc, piece_off, n_pieces, st);
+}
+
+extern "C" int jabba_compress_plain(const double *values, const int64_t *series_off, const int64_t *series_off_host,
+                                    int64_t n_series, int32_t D, double tol, int32_t max_len, int32_t *len,
+                                    double *inc, int64_t *piece_off, int64_t *n_pieces, void *workspace,
+                                    size_t workspace_bytes, void *stream) {
+    if (!series_off_host) return JABBA_EINVAL;
+    const int64_t total_points = n_series >= 0 ? series_off_host[n_series] : -1;
+    int rc = validate(values, series_off, n_series, total_points, D, tol, max_len, len, inc, piece_off, n_pieces);
+    if (rc) return rc;
+    CompressWs w0 = carve_compress(nullptr, n_series, total_points, D);
+    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    CompressWs w = carve_compress(workspace, n_series, total_points, D);
+    hipStream_t st = (hipStream_t)stream;
+    rc = domain_table(w, series_off, n_series, total_points, D, false, st);
+    if (rc) return rc;
+    const int64_t *n_dom_p = w.dom_off + n_series;
+    int64_t d0 = 0;
+    for (int64_t s = 0; s < n_series; ++s) {
+        const int64_t n = series_off_host[s + 1] - series_off_host[s];
+        const int64_t nd = n >= 2 ? (n - 1 + D - 1) / D : 0;
+        if (nd > 0) {
+            rc = launch_compress(64, dim3((unsigned)nd), dim3(kWave), st, values, w, n_dom_p, d0, d0 + nd,
+                                 tol * tol, max_len);
+            if (rc) return rc;
+        }
+        d0 += nd;
+    }
+    return finish(w, n_series, total_points, D, len, inc, piece_off, n_pieces, st);
+}
+
+extern "C" int jabba_workspace_status(const void *workspace, void *stream, int32_t *status) {
+    if (!workspace || !status) return JABBA_EINVAL;
+    int32_t bits = 0;
+    JB_HIP(hipStreamSynchronize((hipStream_t)stream));
+    JB_HIP(hipMemcpy(&bits, workspace, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (bits & kStNonFinite)
+        *status = JABBA_ENONFINITE;
+    else if (bits & kStCapacity)
+        *status = JABBA_ECAPACITY;
+    else if (bits & kStOverflow)
+        *status = JABBA_EOVERFLOW;
+    else if (bits & kStInvalid)
+        *status = JABBA_EINVAL;
+    else
+        *status = JABBA_OK;
+    return JABBA_OK;
+}

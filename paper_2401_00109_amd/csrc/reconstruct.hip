@@ -1,0 +1,299 @@
+// Inverse symbolization (Sec. 3.3): inverse digitization (symbol -> center),
+// quantization of the lengths (Eq. repolygon) and inverse compression.
+//
+// One wavefront per series walks its pieces 64 at a time.
+//  * Quantization: the carry rule keeps sum(len^_1..j) = round(sum(len~_1..j)),
+//    halves away from zero.  Every center length >= 1 is an integer multiple
+//    of 2^-52, so the running sums are exact unsigned 128-bit integers at
+//    scale 2^52: a wavefront inclusive scan plus a carry from the previous
+//    chunk, then S_j = (C_j + 2^51) >> 52 and len^_j = S_j - S_{j-1}.
+//  * Values: V_j = V_{j-1} + inc~_j is a sequential binary64 recurrence; the
+//    wavefront walks it lane by lane (a uniform running value), so every V_j
+//    has the bits of the plain left-to-right evaluation.
+//  * Fill: V_{j-1} + (inc~_j / len^_j) * q for 0 < q < len^_j, then V_j.
+#include "common.h"
+
+namespace jabba {
+namespace {
+
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 shfl_up_u128(u128 v, int d) {
+    unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
+    lo = __shfl_up(lo, d);
+    hi = __shfl_up(hi, d);
+    return ((u128)hi << 64) | lo;
+}
+__device__ __forceinline__ u128 shfl_u128(u128 v, int l) {
+    unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
+    lo = __shfl(lo, l);
+    hi = __shfl(hi, l);
+    return ((u128)hi << 64) | lo;
+}
+__device__ __forceinline__ u128 xor_u128(u128 v, int m) {
+    unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
+    lo = __shfl_xor(lo, m);
+    hi = __shfl_xor(hi, m);
+    return ((u128)hi << 64) | lo;
+}
+
+// d * 2^52 as an exact integer; ok = false when d is negative, not finite or
+// not a multiple of 2^-52 (never the case for means of integer lengths >= 1)
+__device__ __forceinline__ u128 to_fixed(double d, bool &ok) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    const int e = (int)((b >> 52) & 0x7FF);
+    if ((b >> 63) || e == 0x7FF) {
+        ok = false;
+        return 0;
+    }
+    if (e == 0) return 0;  // zero or subnormal: below 2^-52 unless zero
+    const unsigned long long m = (b & ((1ull << 52) - 1)) | (1ull << 52);
+    const int sh = e - 1023;  // d * 2^52 = m * 2^(e - 1023)
+    if (sh >= 0) {
+        if (sh > 60) {
+            ok = false;
+            return 0;
+        }
+        return (u128)m << sh;
+    }
+    if (sh < -52 || (m & ((1ull << -sh) - 1))) {
+        ok = false;
+        return 0;
+    }
+    return (u128)(m >> -sh);
+}
+
+__device__ __forceinline__ int64_t fixed_round(u128 c) { return (int64_t)((c + ((u128)1 << 51)) >> 52); }
+
+struct Src {
+    // dictionary form: symbols + centers; raw form: len/inc (centers == null)
+    const int32_t *sym;
+    const double *center_len;
+    const double *center_inc;
+    int64_t k;
+    const int32_t *len;
+    const double *inc;
+    __device__ void get(int64_t j, u128 &lt, double &it, bool &ok) const {
+        if (center_len) {
+            const int32_t c = sym[j];
+            if (c < 0 || c >= k) {
+                ok = false;
+                lt = (u128)1 << 52;
+                it = 0.0;
+                return;
+            }
+            lt = to_fixed(center_len[c], ok);
+            it = center_inc[c];
+        } else {
+            lt = (u128)(uint32_t)len[j] << 52;
+            it = inc[j];
+        }
+    }
+};
+
+__global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__restrict__ piece_off,
+                                                     const int64_t *__restrict__ series_off, int64_t n_series,
+                                                     int64_t *__restrict__ cnt, int32_t *status) {
+    const int lane = lane_id();
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
+        const int64_t a = piece_off[s], b = piece_off[s + 1];
+        if (b <= a) {
+            if (lane == 0) cnt[s] = (series_off[s + 1] - series_off[s]) >= 1 ? 1 : 0;
+            continue;
+        }
+        u128 acc = 0;
+        bool ok = true;
+        for (int64_t j = a + lane; j < b; j += kWave) {
+            u128 lt;
+            double it;
+            src.get(j, lt, it, ok);
+            acc += lt;
+        }
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) acc += xor_u128(acc, m);
+        if (ballot(!ok) && lane == 0) set_status(status, kStInvalid);
+        if (lane == 0) cnt[s] = 1 + fixed_round(acc);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recon(Src src, const int64_t *__restrict__ piece_off,
+                                               const int64_t *__restrict__ out_off, int64_t n_series,
+                                               const double *__restrict__ t0, double *__restrict__ out,
+                                               int64_t *__restrict__ lhat) {
+    const int lane = lane_id();
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
+        const int64_t a = piece_off[s], b = piece_off[s + 1];
+        const int64_t o = out_off[s];
+        if (out_off[s + 1] > o && lane == 0) out[o] = t0[s];
+        u128 carryC = 0;
+        int64_t carryS = 0;
+        double V = t0[s];
+        for (int64_t j0 = a; j0 < b; j0 += kWave) {
+            const int64_t j = j0 + lane;
+            const bool inr = j < b;
+            u128 lt = 0;
+            double it = 0.0;
+            bool ok = true;
+            if (inr) src.get(j, lt, it, ok);
+            // inclusive scan of the fixed-point center lengths
+            u128 C = lt;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const u128 y = shfl_up_u128(C, d);
+                if (lane >= d) C += y;
+            }
+            C += carryC;
+            const int64_t S = fixed_round(C);
+            int64_t Sp = __shfl_up(S, 1);
+            if (lane == 0) Sp = carryS;
+            const int64_t lh = S - Sp;
+            // sequential running value, lane by lane
+            const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
+            double Vprev = 0.0, Vme = 0.0;
+            for (int l = 0; l < cnt; ++l) {
+                const double il = __shfl(it, l);
+                if (lane == l) Vprev = V;
+                V = V + il;
+                if (lane == l) Vme = V;
+            }
+            if (inr) {
+                if (lhat) lhat[j] = lh;
+                const double slope = it / (double)lh;
+                const int64_t base = o + Sp;
+                for (int64_t q = 1; q < lh; ++q) out[base + q] = Vprev + slope * (double)q;
+                out[o + S] = Vme;
+            }
+            carryC = shfl_u128(C, cnt - 1);
+            carryS = __shfl(S, cnt - 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recon_sse(const int64_t *__restrict__ out_off,
+                                                   const int64_t *__restrict__ series_off, int64_t n_series,
+                                                   const double *__restrict__ values, const double *__restrict__ out,
+                                                   double *__restrict__ sse, int64_t *__restrict__ cnt) {
+    const int lane = lane_id();
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
+        const int64_t n = series_off[s + 1] - series_off[s];
+        const int64_t nh = out_off[s + 1] - out_off[s];
+        const int64_t m = n < nh ? n : nh;
+        double acc = 0.0;
+        for (int64_t i0 = 0; i0 < m; i0 += kWave) {
+            const int64_t i = i0 + lane;
+            double v = 0.0;
+            if (i < m) {
+                const double d = values[series_off[s] + i] - out[out_off[s] + i];
+                v = d * d;
+            }
+            acc = acc + wave_tree_sum(v);
+        }
+        if (lane == 0) {
+            sse[s] = acc;
+            cnt[s] = m;
+        }
+    }
+}
+
+__global__ void k_recon_prep(int32_t *status) {
+    if (threadIdx.x == 0) status[0] = 0;
+}
+
+unsigned waves_grid(int64_t n_series) {
+    int64_t blocks = (n_series * kWave + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    return (unsigned)blocks;
+}
+
+struct ReconWs {
+    int32_t *status;
+    int64_t *cnt;
+    void *scan_ws;
+    size_t bytes;
+};
+
+ReconWs carve_recon(void *ws, int64_t n_series) {
+    Carve c(ws);
+    ReconWs w;
+    w.status = c.take<int32_t>(64);
+    w.cnt = c.take<int64_t>(n_series + 1);
+    w.scan_ws = c.take<char>(scan_workspace(n_series + 1));
+    w.bytes = c.bytes();
+    return w;
+}
+
+int sizes(const Src &src, const int64_t *piece_off, const int64_t *series_off, int64_t n_series, int64_t *out_off,
+          void *workspace, size_t workspace_bytes, hipStream_t st) {
+    if (n_series < 0 || !piece_off || !series_off || !out_off) return JABBA_EINVAL;
+    const ReconWs w0 = carve_recon(nullptr, n_series);
+    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    const ReconWs w = carve_recon(workspace, n_series);
+    hipLaunchKernelGGL(k_recon_prep, dim3(1), dim3(64), 0, st, w.status);
+    JB_LAUNCH_CHECK();
+    if (n_series > 0) {
+        hipLaunchKernelGGL(k_recon_count, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, series_off,
+                           n_series, w.cnt, w.status);
+        JB_LAUNCH_CHECK();
+    }
+    return scan_i64_to_i64(w.cnt, out_off, nullptr, n_series, w.scan_ws, st);
+}
+
+}  // namespace
+}  // namespace jabba
+
+using namespace jabba;
+
+extern "C" int jabba_reconstruct_workspace(int64_t n_series, size_t *bytes) {
+    if (!bytes || n_series < 0) return JABBA_EINVAL;
+    *bytes = carve_recon(nullptr, n_series).bytes;
+    return JABBA_OK;
+}
+
+extern "C" int jabba_reconstruct_size(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off,
+                                      int64_t n_series, const jabba_dict *dict, int64_t *out_off, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+    if (!dict || !dict->center_len || !dict->center_inc) return JABBA_EINVAL;
+    Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
+    return sizes(src, piece_off, series_off, n_series, out_off, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off,
+                                 int64_t n_series, const double *t0, const jabba_dict *dict, const int64_t *out_off,
+                                 double *out, int64_t *lhat, const double *values, double *sse, int64_t *cnt,
+                                 void *stream) {
+    if (!dict || !dict->center_len || !dict->center_inc || n_series < 0 || !piece_off || !out_off) return JABBA_EINVAL;
+    if (n_series == 0) return JABBA_OK;
+    if (!t0 || !out || !series_off) return JABBA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
+    hipLaunchKernelGGL(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
+                       out, lhat);
+    JB_LAUNCH_CHECK();
+    if (values) {
+        if (!sse || !cnt) return JABBA_EINVAL;
+        hipLaunchKernelGGL(k_recon_sse, dim3(waves_grid(n_series)), dim3(256), 0, st, out_off, series_off, n_series,
+                           values, out, sse, cnt);
+        JB_LAUNCH_CHECK();
+    }
+    return JABBA_OK;
+}
+
+extern "C" int jabba_reconstruct_pieces(const int32_t *len, const double *inc, const int64_t *piece_off,
+                                        const int64_t *series_off, int64_t n_series, const double *t0,
+                                        int64_t *out_off, double *out, void *workspace, size_t workspace_bytes,
+                                        void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    Src src{nullptr, nullptr, nullptr, 0, len, inc};
+    int rc = sizes(src, piece_off, series_off, n_series, out_off, workspace, workspace_bytes, st);
+    if (rc || n_series == 0) return rc;
+    if (!t0 || !out) return JABBA_EINVAL;
+    hipLaunchKernelGGL(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
+                       out, (int64_t *)nullptr);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}

@@ -1,0 +1,343 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by
+element on the same seeded inputs.
+
+Bar: bit-exact for piece lengths, increments, piece offsets, sigma, sort
+blocks, starting points, symbols, k, counts, center lengths, quantized
+lengths and reconstructions given the same dictionary; center increments
+(a sum over up to ~1e5 members in a different fixed order) within 1e-12 of
+max(|mean|, mean |inc|) of the group.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_00109_amd.inputs import make_workload, pack, random_walk, series_rng, znorm
+
+from gpu_util import DEV, assert_centers_close, gpu_compress, gpu_digitize, say, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {1: 1.0, 2: 0.01, 3: 0.002, 4: 1.0 / 256}
+
+
+def _workload(wid):
+    return make_workload(wid, seed=0, scale=SMALL[wid])
+
+
+# ------------------------------------------------------------------ numerics
+def test_fp64_division_and_sqrt_are_correctly_rounded():
+    import ctypes as C
+    import paper_2401_00109_amd as J
+    T = torch()
+    rng = np.random.default_rng(0)
+    n = 1 << 21
+    a = np.abs(rng.standard_normal(n)) * np.exp2(rng.integers(-200, 200, n))
+    b = rng.standard_normal(n) * np.exp2(rng.integers(-200, 200, n))
+    edge = np.array([1.0, 2.0, 4.0, 0.0, 1e-310, 2.0 ** -1074, 1.7976931348623157e308, 0.5, 3.0, 1e16, 1e-16, 9.0])
+    a = np.concatenate([a, edge, np.arange(1, 5000, dtype=np.float64)])
+    b = np.concatenate([b, np.resize(np.array([3.0, 7.0, -1.0, 1e-300, 5.0]), edge.size + 4999)])
+    da, db = to_dev(a), to_dev(b)
+    q = T.empty_like(da)
+    r = T.empty_like(da)
+    say(f"fp64 selftest n={a.size}")
+    rc = J.lib().jabba_fp64_selftest(C.c_void_p(da.data_ptr()), C.c_void_p(db.data_ptr()), C.c_void_p(q.data_ptr()),
+                                     C.c_void_p(r.data_ptr()), a.size, C.c_void_p(T.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    T.cuda.synchronize()
+    np.testing.assert_array_equal(q.cpu().numpy().view(np.uint64), (a / b).view(np.uint64))
+    np.testing.assert_array_equal(r.cpu().numpy().view(np.uint64), np.sqrt(a).view(np.uint64))
+
+
+# ------------------------------------------------------------------ compress
+@pytest.mark.parametrize("wid", [1, 2, 3, 4])
+def test_compress_parity(wid):
+    w = _workload(wid)
+    say(f"compress workload {wid}: {w.n_series} series {w.n_points} points D={w.D} tol={w.tol}")
+    ln, inc, po, st = gpu_compress(w.values, w.series_off, w.D, w.tol)
+    assert st == 0
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    np.testing.assert_array_equal(po, opo)
+    np.testing.assert_array_equal(ln, ol)
+    np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+
+
+@pytest.mark.parametrize("W", [1, 2, 4, 8, 16, 32, 64])
+def test_compress_lane_width_never_changes_results(W):
+    w = _workload(2)
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    for wpb, bpc in [(1, 1), (4, 8), (16, 2)]:
+        say(f"compress W={W} waves_per_block={wpb} blocks_per_cu={bpc}")
+        ln, inc, po, st = gpu_compress(w.values, w.series_off, w.D, w.tol,
+                                       tuning={"lanes_per_domain": W, "waves_per_block": wpb, "blocks_per_cu": bpc})
+        assert st == 0
+        np.testing.assert_array_equal(ln, ol)
+        np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+        np.testing.assert_array_equal(po, opo)
+
+
+def test_compress_plain_launches_equal_batched():
+    w = _workload(3)
+    say("compress plain per-series launches")
+    ln, inc, po, st = gpu_compress(w.values, w.series_off, w.D, w.tol, plain=True)
+    assert st == 0
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    np.testing.assert_array_equal(ln, ol)
+    np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+    np.testing.assert_array_equal(po, opo)
+
+
+@pytest.mark.parametrize("case", ["degenerate_lengths", "straight", "tol0_pwl", "max_len", "D1", "constant",
+                                  "long_domains"])
+def test_compress_edge_cases(case):
+    rng = np.random.default_rng(5)
+    D, tol, max_len = 7, 0.1, 0
+    if case == "degenerate_lengths":
+        lens = [0, 1, 2, 3, 0, 8, 1, 65, 64, 63, 129]
+        vals, off = pack([rng.standard_normal(n) for n in lens])
+    elif case == "straight":
+        vals, off = pack([3.0 + 0.25 * np.arange(n) for n in (5, 100, 1001, 2)])
+        D, tol = 100, 0.0
+    elif case == "tol0_pwl":
+        v = np.concatenate([np.arange(0, 50) * 2.0, 98.0 - np.arange(1, 70) * 3.0])
+        vals, off = pack([v, v[::-1].copy()])
+        D, tol = 1000, 0.0
+    elif case == "max_len":
+        vals, off = pack([np.cumsum(rng.standard_normal(500)) * 0.01])
+        D, tol, max_len = 1000, 10.0, 5
+    elif case == "D1":
+        vals, off = pack([rng.standard_normal(50)])
+        D = 1
+    elif case == "constant":
+        vals, off = pack([np.full(300, 2.5), np.zeros(70)])
+        D, tol = 64, 0.0
+    else:  # domains far longer than a wavefront's 64 candidates
+        vals, off = pack([np.linspace(0, 1, 3000) + 1e-9 * rng.standard_normal(3000)])
+        D, tol = 2999, 0.01
+    say(f"compress edge case {case}")
+    for W in (1, 4, 64):
+        ln, inc, po, st = gpu_compress(vals, off, D, tol, max_len, tuning={"lanes_per_domain": W})
+        assert st == 0
+        ol, oi, opo = O.compress(vals, off, D, tol, max_len)
+        np.testing.assert_array_equal(po, opo)
+        np.testing.assert_array_equal(ln, ol)
+        np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+
+
+def test_compress_empty_input():
+    say("compress empty input")
+    ln, inc, po, st = gpu_compress(np.zeros(0), np.zeros(1, np.int64), 10, 0.1)
+    assert ln.size == 0 and po.tolist() == [0] and st == 0
+
+
+def test_compress_nonfinite_sets_device_status():
+    from paper_2401_00109_amd import _lib
+    v = np.cumsum(np.random.default_rng(1).standard_normal(2000))
+    v[777] = np.nan
+    say("compress with a NaN value")
+    _, _, _, st = gpu_compress(v, np.array([0, 2000]), 100, 0.1)
+    assert st == _lib.JABBA_ENONFINITE
+    v[777] = np.inf
+    _, _, _, st = gpu_compress(v, np.array([0, 2000]), 100, 0.1)
+    assert st == _lib.JABBA_ENONFINITE
+
+
+# ------------------------------------------------------------------ digitize
+def _pieces(wid):
+    w = _workload(wid)
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    return w, ol, oi, opo
+
+
+@pytest.mark.parametrize("wid", [1, 2, 3, 4])
+@pytest.mark.parametrize("B", [1, 7, 256, 4096, 10**9])
+def test_digitize_parity(wid, B):
+    w, ol, oi, _ = _pieces(wid)
+    say(f"digitize workload {wid} N={ol.size} B={B} alpha={w.alpha}")
+    sym, d, st = gpu_digitize(ol, oi, w.alpha, w.scl, B)
+    assert st == 0
+    od = O.digitize(ol, oi, w.alpha, w.scl, B)
+    assert d["sigma_len"] == od.sigma_len and d["sigma_inc"] == od.sigma_inc
+    assert d["k"] == od.k
+    np.testing.assert_array_equal(sym, od.symbols)
+    np.testing.assert_array_equal(d["count"], od.count)
+    np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
+    np.testing.assert_array_equal(d["cx"].view(np.uint64), od.cx.view(np.uint64))
+    worst = assert_centers_close(d, od, oi, od.symbols)
+    say(f"  k={od.k} G={od.n_starts} center_inc worst rel err {worst:.3e}")
+
+
+@pytest.mark.parametrize("case", ["one_piece", "identical", "alpha0", "ties_across_blocks", "scl0", "big_tie_block"])
+def test_digitize_edge_cases(case):
+    rng = np.random.default_rng(11)
+    alpha, scl, B = 0.1, 1.0, 16
+    if case == "one_piece":
+        ln, inc = np.array([3], np.int32), np.array([0.25])
+    elif case == "identical":
+        ln, inc = np.full(500, 2, np.int32), np.full(500, -0.5)
+    elif case == "alpha0":
+        ln = rng.integers(1, 5, 3000).astype(np.int32)
+        inc = np.round(rng.standard_normal(3000), 1)
+        alpha = 0.0
+    elif case == "ties_across_blocks":
+        ln = rng.integers(1, 3, 4000).astype(np.int32)
+        inc = rng.integers(-2, 3, 4000) * 0.5
+        B = 64
+    elif case == "scl0":
+        ln = rng.integers(1, 9, 2000).astype(np.int32)
+        inc = rng.standard_normal(2000)
+        scl = 0.0
+    else:  # more equal keys than one LDS bitmap holds
+        ln = np.ones(80_000, np.int32)
+        inc = np.where(rng.random(80_000) < 0.9, 0.25, -0.75)
+        B, alpha = 1024, 0.05
+    say(f"digitize edge case {case}")
+    sym, d, st = gpu_digitize(ln, inc, alpha, scl, B)
+    assert st == 0
+    od = O.digitize(ln, inc, alpha, scl, B)
+    assert d["k"] == od.k
+    np.testing.assert_array_equal(sym, od.symbols)
+    np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
+    assert_centers_close(d, od, inc, od.symbols)
+
+
+def test_digitize_capacity_status():
+    from paper_2401_00109_amd import _lib
+    w, ol, oi, _ = _pieces(1)
+    say("digitize with a too-small dictionary")
+    sym, d, st = gpu_digitize(ol, oi, w.alpha, 1.0, 4096, capacity=10)
+    assert st == _lib.JABBA_ECAPACITY
+    od = O.digitize(ol, oi, w.alpha, 1.0, 4096)
+    assert d["k"] == od.k
+    np.testing.assert_array_equal(sym, od.symbols)
+
+
+def test_digitize_stage1_waves_never_change_results():
+    w, ol, oi, _ = _pieces(2)
+    od = O.digitize(ol, oi, w.alpha, w.scl, 512)
+    for s1 in (1, 2, 8, 16):
+        say(f"digitize stage1_waves={s1}")
+        sym, d, st = gpu_digitize(ol, oi, w.alpha, w.scl, 512, tuning={"stage1_waves": s1})
+        np.testing.assert_array_equal(sym, od.symbols)
+
+
+# ------------------------------------------------------------------ encode
+@pytest.mark.parametrize("wid", [1, 2])
+def test_encode_parity(wid):
+    import paper_2401_00109_amd as J
+    T = torch()
+    w1 = _workload(1)
+    l1, i1, _ = O.compress(w1.values, w1.series_off, w1.D, w1.tol)
+    od = O.digitize(l1, i1, w1.alpha, 1.0, 4096)
+    w, ol, oi, _ = _pieces(wid)
+    say(f"encode workload {wid} ({ol.size} pieces) against k={od.k}")
+    d = J.Dictionary.from_host(od.sigma_len, od.sigma_inc, od.scl, od.alpha, od.center_len, od.center_inc, od.cx,
+                               od.cy, od.count, DEV)
+    L, I = to_dev(ol), to_dev(oi)
+    npc = T.tensor([ol.size], dtype=T.int64, device=DEV)
+    sym = J.encode(L, I, npc, ol.size, d)
+    T.cuda.synchronize()
+    exp = O.encode(ol, oi, od.sigma_len, od.sigma_inc, od.scl, od.cx, od.cy)
+    np.testing.assert_array_equal(sym[: ol.size].cpu().numpy(), exp)
+
+
+# ------------------------------------------------------------------ reconstruct
+@pytest.mark.parametrize("wid", [1, 3])
+def test_reconstruct_parity(wid):
+    import paper_2401_00109_amd as J
+    w, ol, oi, opo = _pieces(wid)
+    od = O.digitize(ol, oi, w.alpha, 1.0, 4096)
+    t0 = w.values[w.series_off[:-1]] if w.n_series else np.zeros(0)
+    t0 = np.where(np.diff(w.series_off) > 0, t0, 0.0)
+    out, oo, lhat, sse, cnt = O.reconstruct(od.symbols, opo, w.series_off, t0, od.center_len, od.center_inc,
+                                            orig=w.values)
+    say(f"reconstruct workload {wid}: {out.size} points")
+    d = J.Dictionary.from_host(od.sigma_len, od.sigma_inc, od.scl, od.alpha, od.center_len, od.center_inc, od.cx,
+                               od.cy, od.count, DEV)
+    r = J.reconstruct(to_dev(od.symbols), to_dev(opo), to_dev(w.series_off), to_dev(t0), d, values=to_dev(w.values),
+                      want_lhat=True)
+    assert r["status"] == 0
+    np.testing.assert_array_equal(r["out_off"].cpu().numpy(), oo)
+    np.testing.assert_array_equal(r["lhat"][: ol.size].cpu().numpy(), lhat)
+    np.testing.assert_array_equal(r["out"].cpu().numpy().view(np.uint64), out.view(np.uint64))
+    np.testing.assert_array_equal(r["cnt"].cpu().numpy()[: w.n_series], cnt)
+    np.testing.assert_allclose(r["sse"].cpu().numpy()[: w.n_series], sse, rtol=1e-12, atol=1e-300)
+
+
+def test_reconstruct_pieces_parity():
+    import paper_2401_00109_amd as J
+    w, ol, oi, opo = _pieces(2)
+    t0 = w.values[w.series_off[:-1]]
+    out, oo = O.reconstruct_pieces(ol, oi, opo, t0)
+    say("reconstruct from raw pieces")
+    g, go = J.reconstruct_pieces(to_dev(ol), to_dev(oi), to_dev(opo), to_dev(w.series_off), to_dev(t0))
+    np.testing.assert_array_equal(go.cpu().numpy(), oo)
+    np.testing.assert_array_equal(g[: out.size].cpu().numpy().view(np.uint64), out.view(np.uint64))
+
+
+def test_reconstruct_half_lengths():
+    import paper_2401_00109_amd as J
+    sym = np.array([0, 1, 0], np.int32)
+    po = np.array([0, 3], np.int64)
+    off = np.array([0, 9], np.int64)
+    cl, ci = np.array([1.5, 2.5]), np.array([1.0, -1.0])
+    d = J.Dictionary.from_host(1.0, 1.0, 1.0, 0.1, cl, ci, cl, ci, device=DEV)
+    say("reconstruct halves")
+    r = J.reconstruct(to_dev(sym), to_dev(po), to_dev(off), to_dev(np.array([0.0])), d, want_lhat=True)
+    assert r["lhat"][:3].cpu().tolist() == [2, 2, 2]
+    assert r["out"].cpu().tolist() == [0.0, 0.5, 1.0, 0.5, 0.0, 0.5, 1.0]
+
+
+# ------------------------------------------------------------------ graph plan
+def test_plan_graph_replays_match_eager():
+    import paper_2401_00109_amd as J
+    T = torch()
+    w = _workload(3)
+    v, so = to_dev(w.values), to_dev(w.series_off)
+    say(f"plan capture: {w.n_series} series")
+    plan = J.Plan(v, so, w.D, w.tol, w.alpha, w.scl, w.B, tuning={"lanes_per_domain": 4})
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    od = O.digitize(ol, oi, w.alpha, w.scl, w.B)
+    for rep in range(3):
+        plan.pieces.len.fill_(-1)
+        plan.symbols.fill_(-1)
+        T.cuda.synchronize()
+        plan.run()
+        T.cuda.synchronize()
+        say(f"  replay {rep}")
+        ln, inc, po = plan.pieces.host()
+        np.testing.assert_array_equal(ln, ol)
+        np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+        np.testing.assert_array_equal(plan.symbols[: ol.size].cpu().numpy(), od.symbols)
+        assert plan.dictionary.size() == od.k
+        # eager work between replays
+        J.compress(v, so, w.D, w.tol)
+        T.cuda.synchronize()
+    assert plan.status() == (0, 0)
+    plan.close()
+
+
+# ------------------------------------------------------------------ full size
+def test_full_size_scale_workload():
+    """4,096 x 10,000 points, the launch configuration the benchmark times."""
+    import paper_2401_00109_amd as J
+    T = torch()
+    w = make_workload(2, seed=0)
+    say(f"full-size workload 2: {w.n_series} series, {w.n_points} points")
+    v, so = to_dev(w.values), to_dev(w.series_off)
+    sz = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B)
+    sz.run(v, so)
+    T.cuda.synchronize()
+    assert sz.status() == (0, 0)
+    ln, inc, po = sz.pieces.host()
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    np.testing.assert_array_equal(po, opo)
+    np.testing.assert_array_equal(ln, ol)
+    np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+    say(f"  compress parity ok: N={ol.size}; running the oracle's digitize")
+    od = O.digitize(ol, oi, w.alpha, w.scl, w.B)
+    d = sz.dictionary.host()
+    assert d["k"] == od.k
+    np.testing.assert_array_equal(sz.symbols[: ol.size].cpu().numpy(), od.symbols)
+    np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
+    worst = assert_centers_close(d, od, oi, od.symbols)
+    say(f"  digitize parity ok: k={od.k} G={od.n_starts} center_inc worst rel {worst:.3e}")
