@@ -77,7 +77,8 @@ typedef struct jabba_tuning {
     int32_t lanes_per_domain; /* compress: lanes that test candidate end points of one
                                  domain together; 1, 2, 4, 8, 16, 32 or 64 (64 = one
                                  wavefront per domain)                                  */
-    int32_t waves_per_block;  /* compress: wavefronts per workgroup, 1..16              */
+    int32_t waves_per_block;  /* compress: wavefronts per workgroup, 1..16 (lowered when
+                                 the workgroup's staging buffers would exceed 64 KB)   */
     int32_t blocks_per_cu;    /* compress: persistent workgroups per compute unit, 1..32 */
     int32_t stage1_waves;     /* digitize Stage I: wavefronts per workgroup (one block
                                  of sorted pieces per wavefront), 1..16                 */
@@ -196,6 +197,14 @@ int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_piece
                    void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Counters of the last jabba_digitize that used `workspace` (same max_pieces
+ * and B): stats[0] = N pieces, stats[1] = G Stage I starting points,
+ * stats[2] = k symbols, stats[3] = radix passes that moved data (digits that
+ * are equal in every key are skipped).  Synchronises `stream`.
+ */
+int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream, int64_t *stats);
+
+/*
  * Nearest-center digitization against an existing dictionary (Sec. 3.2,
  * c* = argmin_c ||p - c||, f_d = I_d(c*)): x = params[2]*(len/params[0]),
  * y = inc/params[1], symbol = argmin_c (x - cx_c)^2 + (y - cy_c)^2 over all
@@ -269,6 +278,20 @@ int jabba_workspace_status(const void *workspace, void *stream, int32_t *status)
  * decisions rely on.  n >= 0 elements, device arrays.
  */
 int jabba_fp64_selftest(const double *a, const double *b, double *quot, double *root, int64_t n, void *stream);
+
+/*
+ * Per-kernel timing for benchmarks.  While enabled, every kernel launch of
+ * the library is bracketed by two HIP events recorded on the stream the
+ * kernel is launched on; durations accumulate per kernel name.  Enabling
+ * clears the accumulators.  Must be off while a plan is being captured.
+ * jabba_timing_get synchronises on the recorded events; *launches is the
+ * number of timed launches of `name` (0 if none).  jabba_timing_names writes
+ * the kernel names seen so far, comma-separated, into buf (truncated to
+ * buf_len - 1 characters).
+ */
+int jabba_timing_enable(int enable);
+int jabba_timing_get(const char *name, double *total_ms, int64_t *launches);
+int jabba_timing_names(char *buf, size_t buf_len);
 
 /* ------------------------------------------------------------------------ */
 /* Batched plan: the whole compress + digitize path captured once into a HIP  */

@@ -27,6 +27,7 @@ EXPORTS = [
     "jabba_digitize_workspace", "jabba_digitize", "jabba_encode", "jabba_reconstruct_workspace",
     "jabba_reconstruct_size", "jabba_reconstruct", "jabba_reconstruct_pieces", "jabba_workspace_status",
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
+    "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
 ]
 
 
@@ -95,6 +96,10 @@ def lib() -> C.CDLL:
             L.jabba_plan_run.argtypes = [P, P]
             L.jabba_plan_destroy.argtypes = [P]
             L.jabba_fp64_selftest.argtypes = [P, P, P, P, I64, P]
+            L.jabba_digitize_stats.argtypes = [P, I64, I32, P, C.POINTER(I64)]
+            L.jabba_timing_enable.argtypes = [C.c_int]
+            L.jabba_timing_get.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(I64)]
+            L.jabba_timing_names.argtypes = [C.c_char_p, SZ]
             for name in EXPORTS:
                 if name != "jabba_status_str":
                     getattr(L, name).restype = C.c_int

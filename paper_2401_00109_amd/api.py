@@ -17,7 +17,8 @@ from . import _lib as L
 
 __all__ = [
     "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "reconstruct",
-    "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer",
+    "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
+    "timing_enable", "timing_report", "digitize_stats",
 ]
 
 
@@ -152,6 +153,14 @@ class Dictionary:
         z = np.load(path, allow_pickle=False)
         return cls.from_host(float(z["sigma_len"]), float(z["sigma_inc"]), float(z["scl"]), float(z["alpha"]),
                              z["center_len"], z["center_inc"], z["cx"], z["cy"], z["count"], device)
+
+
+def digitize_stats(workspace: torch.Tensor, max_pieces: int, B: int, stream=None) -> dict:
+    """N, G (Stage I starting points), k and active radix passes of the last digitize on this workspace."""
+    arr = (C.c_int64 * 4)()
+    L.check(L.lib().jabba_digitize_stats(_p(workspace), int(max_pieces), int(B), _stream(stream), arr),
+            "jabba_digitize_stats")
+    return {"N": arr[0], "G": arr[1], "k": arr[2], "sort_passes": arr[3]}
 
 
 def workspace_status(ws: torch.Tensor, stream=None) -> int:
@@ -376,3 +385,70 @@ class Symbolizer:
 
     def status(self) -> tuple[int, int]:
         return workspace_status(self.cws), workspace_status(self.dws)
+
+    def stats(self) -> dict:
+        return digitize_stats(self.dws, self.max_pieces, self.B)
+
+
+class Reconstructor:
+    """Preallocated inverse symbolization for a fixed set of series.
+
+    size() runs the size pass and synchronises once to allocate the output;
+    run() then enqueues size + fill without any host synchronisation (valid
+    while the symbols describe the same total length, e.g. a repeated batch).
+    """
+
+    def __init__(self, piece_off: torch.Tensor, series_off: torch.Tensor, t0: torch.Tensor,
+                 values: torch.Tensor | None = None):
+        dev = piece_off.device
+        self.piece_off, self.series_off, self.t0, self.values = piece_off, series_off, t0, values
+        self.ns = piece_off.numel() - 1
+        self.ws = _ws(recon_workspace_bytes(self.ns), dev)
+        self.out_off = torch.empty(self.ns + 1, dtype=torch.int64, device=dev)
+        self.sse = torch.empty(max(self.ns, 1), dtype=torch.float64, device=dev)
+        self.cnt = torch.empty(max(self.ns, 1), dtype=torch.int64, device=dev)
+        self.out = None
+
+    def _size(self, symbols, dictionary, stream=None):
+        d = dictionary.struct()
+        L.check(L.lib().jabba_reconstruct_size(_p(symbols), _p(self.piece_off), _p(self.series_off), self.ns,
+                                               C.byref(d), _p(self.out_off), _p(self.ws), self.ws.numel(),
+                                               _stream(stream)), "jabba_reconstruct_size")
+
+    def size(self, symbols, dictionary, stream=None) -> int:
+        self._size(symbols, dictionary, stream)
+        total = int(self.out_off[-1].item())
+        if self.out is None or self.out.numel() < total:
+            self.out = torch.empty(max(total, 1), dtype=torch.float64, device=self.piece_off.device)
+        return total
+
+    def run(self, symbols, dictionary, stream=None):
+        self._size(symbols, dictionary, stream)
+        d = dictionary.struct()
+        v = self.values
+        L.check(L.lib().jabba_reconstruct(_p(symbols), _p(self.piece_off), _p(self.series_off), self.ns, _p(self.t0),
+                                          C.byref(d), _p(self.out_off), _p(self.out), None, _p(v),
+                                          _p(self.sse) if v is not None else None,
+                                          _p(self.cnt) if v is not None else None, _stream(stream)),
+                "jabba_reconstruct")
+
+    def mse(self) -> float:
+        c = int(self.cnt[: self.ns].sum().item())
+        return float(self.sse[: self.ns].sum().item()) / max(c, 1)
+
+
+def timing_enable(on: bool = True) -> None:
+    """Per-kernel HIP-event timing inside the library (see jabba_timing_enable)."""
+    L.check(L.lib().jabba_timing_enable(1 if on else 0), "jabba_timing_enable")
+
+
+def timing_report() -> dict:
+    """{kernel name: (total ms, launches)} accumulated since timing_enable(True)."""
+    buf = C.create_string_buffer(1 << 16)
+    L.check(L.lib().jabba_timing_names(buf, len(buf)), "jabba_timing_names")
+    out = {}
+    for name in filter(None, buf.value.decode().split(",")):
+        ms, n = C.c_double(), C.c_int64()
+        L.check(L.lib().jabba_timing_get(name.encode(), C.byref(ms), C.byref(n)), "jabba_timing_get")
+        out[name] = (ms.value, n.value)
+    return out

@@ -2,7 +2,76 @@
 // per-device facts the launchers size their grids with.
 #include "common.h"
 
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
 namespace jabba {
+
+namespace {
+struct TimingSlot {
+    double ms = 0.0;
+    int64_t launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+std::atomic<bool> g_timing{false};
+std::mutex g_tmu;
+std::map<std::string, TimingSlot> g_slots;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t ev_get() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+std::string clean_name(const char *n) {
+    std::string s(n);
+    std::string o;
+    for (char ch : s)
+        if (ch != '(' && ch != ')' && ch != ' ') o += ch;
+    const size_t c = o.rfind("::");
+    return c == std::string::npos ? o : o.substr(c + 2);
+}
+
+void settle(TimingSlot &t) {
+    for (auto &pr : t.pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+            t.ms += ms;
+            t.launches += 1;
+        }
+        g_pool.push_back(pr.first);
+        g_pool.push_back(pr.second);
+    }
+    t.pending.clear();
+}
+}  // namespace
+
+KernelTimer::KernelTimer(const char *name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
+    if (!g_timing.load(std::memory_order_relaxed)) return;
+    std::lock_guard<std::mutex> g(g_tmu);
+    hipEvent_t e = ev_get();
+    if (e && hipEventRecord(e, st) == hipSuccess) a_ = e;
+}
+
+KernelTimer::~KernelTimer() {
+    if (!a_) return;
+    std::lock_guard<std::mutex> g(g_tmu);
+    hipEvent_t e = ev_get();
+    if (e && hipEventRecord(e, st_) == hipSuccess)
+        g_slots[clean_name(name_)].pending.emplace_back((hipEvent_t)a_, e);
+    else
+        g_pool.push_back((hipEvent_t)a_);
+}
 
 int device_cu_count() {
     static int cache[64] = {0};
@@ -34,9 +103,46 @@ extern "C" int jabba_fp64_selftest(const double *a, const double *b, double *quo
     if (n == 0) return JABBA_OK;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(jabba::k_fp64_selftest, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a, b, quot,
+    JB_LAUNCH(jabba::k_fp64_selftest, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a, b, quot,
                        root, n);
     JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
+
+extern "C" int jabba_timing_enable(int enable) {
+    std::lock_guard<std::mutex> g(jabba::g_tmu);
+    for (auto &kv : jabba::g_slots) jabba::settle(kv.second);
+    if (enable) jabba::g_slots.clear();
+    jabba::g_timing.store(enable != 0);
+    return JABBA_OK;
+}
+
+extern "C" int jabba_timing_get(const char *name, double *total_ms, int64_t *launches) {
+    if (!name || !total_ms || !launches) return JABBA_EINVAL;
+    std::lock_guard<std::mutex> g(jabba::g_tmu);
+    auto it = jabba::g_slots.find(name);
+    if (it == jabba::g_slots.end()) {
+        *total_ms = 0.0;
+        *launches = 0;
+        return JABBA_OK;
+    }
+    jabba::settle(it->second);
+    *total_ms = it->second.ms;
+    *launches = it->second.launches;
+    return JABBA_OK;
+}
+
+extern "C" int jabba_timing_names(char *buf, size_t buf_len) {
+    if (!buf || buf_len == 0) return JABBA_EINVAL;
+    std::lock_guard<std::mutex> g(jabba::g_tmu);
+    std::string all;
+    for (auto &kv : jabba::g_slots) {
+        if (!all.empty()) all += ",";
+        all += kv.first;
+    }
+    size_t n = all.size() < buf_len - 1 ? all.size() : buf_len - 1;
+    for (size_t i = 0; i < n; ++i) buf[i] = all[i];
+    buf[n] = 0;
     return JABBA_OK;
 }
 

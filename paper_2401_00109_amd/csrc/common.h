@@ -54,6 +54,23 @@ struct Carve {
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
+// Opt-in per-kernel event timing (jabba_timing_*): a scope that records an
+// event on `st` when created and another when destroyed, if timing is on.
+struct KernelTimer {
+    KernelTimer(const char *name, hipStream_t st);
+    ~KernelTimer();
+    const char *name_;
+    hipStream_t st_;
+    void *a_;
+};
+// Launch with the optional event timing around it (the kernel expression's
+// text is the timing name).
+#define JB_LAUNCH(kernel, grid, block, lds, st, ...)                   \
+    do {                                                               \
+        ::jabba::KernelTimer jb_timer_(#kernel, st);                   \
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__); \
+    } while (0)
+
 // ---------------------------------------------------------------- device side
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

@@ -21,6 +21,7 @@
 // atomic work queue ordered by domain length (longest first), so the launch
 // is persistent and balances uneven series.
 #include "common.h"
+#include "compress_filter.h"
 
 namespace jabba {
 
@@ -87,6 +88,18 @@ __global__ void k_prepare(int32_t *status, int32_t *q_head) {
     }
 }
 
+// Ring of staged points per group (positions p live in slot p & (R - 1)).
+template <int W>
+struct RingShape {
+    static constexpr int R = W >= 4 ? 128 : (W == 2 ? 64 : 32);
+    static constexpr int Q = R / 2;  // refill granularity
+};
+
+template <int W>
+size_t compress_lds_per_wave() {
+    return (size_t)(kWave / W) * RingShape<W>::R * sizeof(double);
+}
+
 template <int W>
 __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t, const Dom *__restrict__ doms,
                                                    const int32_t *__restrict__ queue,
@@ -95,10 +108,14 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
                                                    int32_t max_len, int32_t *__restrict__ st_len,
                                                    double *__restrict__ st_inc, int32_t *__restrict__ dom_count,
                                                    int32_t *status) {
+    constexpr int R = RingShape<W>::R;
+    constexpr int Q = RingShape<W>::Q;
+    extern __shared__ double ring_all[];
     const int lane = lane_id();
     const int j = lane & (W - 1);
     const int leader = lane - j;
     const uint64_t gmask = (W == 64) ? ~0ull : (((1ull << W) - 1ull) << leader);
+    double *ring = ring_all + (size_t)(threadIdx.x / kWave) * (kWave / W) * R + (size_t)(lane / W) * R;
     const int64_t n_dom = *n_dom_p;
     const bool direct = direct_base >= 0;
     const int64_t wave_g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -106,33 +123,34 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     // group state, replicated over the group's lanes
     int32_t dom = -1;
     bool exhausted = false;
-    int64_t s = 0, e = 0, obase = 0;
+    int64_t s = 0, e = 0, obase = 0, le = 0;
     int32_t np = 0;
     double ts = 0.0;
     int32_t c0 = 2;
-    int32_t k = 1;
-    // lane state: candidate length c of this lane in the current round
-    int32_t c = 0;
-    bool valid = false;
-    double slope = 0.0, acc = 0.0, thr = 0.0;
-    bool setup = false;
+    double S2c = 0.0, S1c = 0.0;  // sums over the terms of candidates below c0
+
+    auto start_domain = [&](int32_t d) {
+        dom = d;
+        const Dom x = doms[dom];
+        s = x.start;
+        e = x.start + x.nint;
+        obase = x.start;
+        le = x.start;
+        np = 0;
+        ts = t[s];
+        if (j == 0 && !isfinite(ts)) set_status(status, kStNonFinite);
+        c0 = 2;
+        S2c = 0.0;
+        S1c = 0.0;
+    };
+    // point p (s <= p <= e) of the current domain: staged or, for pieces
+    // longer than the ring holds, straight from memory
+    auto at = [&](int64_t p) -> double { return p < le ? ring[p & (R - 1)] : t[p]; };
 
     if (direct) {
-        // one domain per group, no queue
-        int64_t d = direct_base + wave_g * (kWave / W) + lane / W;
+        const int64_t d = direct_base + wave_g * (kWave / W) + lane / W;
         exhausted = true;
-        if (d < direct_end) {
-            dom = (int32_t)d;
-            Dom x = doms[dom];
-            s = x.start;
-            e = x.start + x.nint;
-            obase = x.start;
-            np = 0;
-            ts = t[s];
-            if (j == 0 && !isfinite(ts)) set_status(status, kStNonFinite);
-            c0 = 2;
-            setup = true;
-        }
+        if (d < direct_end) start_domain((int32_t)d);
     }
 
     for (;;) {
@@ -147,7 +165,7 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
                 int got = dom;
                 bool ex = exhausted;
                 if (need) {
-                    int64_t qp = (int64_t)base + __popcll(nm & lanemask_lt());
+                    const int64_t qp = (int64_t)base + __popcll(nm & lanemask_lt());
                     if (qp < n_dom)
                         got = queue[qp];
                     else
@@ -155,57 +173,75 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
                 }
                 got = shfl_i(got, leader);
                 ex = shfl_i((int)ex, leader) != 0;
-                if (got >= 0 && dom < 0) {
-                    dom = got;
-                    Dom x = doms[dom];
-                    s = x.start;
-                    e = x.start + x.nint;
-                    obase = x.start;
-                    np = 0;
-                    ts = t[s];
-                    if (j == 0 && !isfinite(ts)) set_status(status, kStNonFinite);
-                    c0 = 2;
-                    setup = true;
-                }
+                if (got >= 0 && dom < 0) start_domain(got);
                 exhausted = ex;
             }
-        }
-        if (setup) {
-            c = c0 + j;
-            valid = (s + c <= e) && (max_len <= 0 || c <= max_len);
-            if (valid) {
-                const double te = t[s + c];
-                slope = (te - ts) / (double)c;
-                thr = (double)(c - 1) * tol2;
-            }
-            acc = 0.0;
-            k = 1;
-            setup = false;
         }
         const bool act = dom >= 0;
         if (ballot(act || !exhausted) == 0ull) break;
 
-        // one interior term of this lane's candidate
-        if (act && valid && k < c) {
-            double v = slope * (double)k;
-            v = ts + v;
-            const double r = v - t[s + k];
-            acc = acc + r * r;
+        int verdict = -1;  // per lane: +1 accept, -1 reject
+        int32_t c = 0;
+        double S2 = 0.0, S1 = 0.0;
+        if (act) {
+            // stage the points this round reads: [s + c0 - 1, s + c0 + W - 1]
+            int64_t need_hi = s + c0 + W - 1;
+            if (need_hi > e) need_hi = e;
+            while (le <= need_hi && le + Q - R <= s) {
+                for (int m = j; m < Q; m += W) {
+                    const int64_t p = le + m;
+                    if (p <= e) ring[p & (R - 1)] = t[p];
+                }
+                le += Q;
+            }
+            c = c0 + j;
+            const int64_t pk = s + c - 1;  // the term this candidate adds: k = c - 1
+            double a2 = 0.0, a1 = 0.0;
+            if (pk <= e) {
+                const double d = at(pk) - ts;
+                a2 = d * d;
+                a1 = (double)(c - 1) * d;
+            }
+            S2 = a2;
+            S1 = a1;
+#pragma unroll
+            for (int o = 1; o < W; o <<= 1) {
+                const double y2 = __shfl_up(S2, o, W);
+                const double y1 = __shfl_up(S1, o, W);
+                if (j >= o) {
+                    S2 += y2;
+                    S1 += y1;
+                }
+            }
+            S2 += S2c;
+            S1 += S1c;
+            const bool valid = (s + c <= e) && (max_len <= 0 || c <= max_len);
+            if (valid) {
+                const double te = at(s + c);
+                const double b = (te - ts) / (double)c;
+                const double thr = (double)(c - 1) * tol2;
+                verdict = filter_decide(S2, S1, b, ts, c, thr);
+                if (verdict == 0) {
+                    // undecided by the bound: evaluate the definition itself
+                    double acc = 0.0;
+                    for (int32_t k = 1; k < c; ++k) {
+                        double v = b * (double)k;
+                        v = ts + v;
+                        const double r = v - at(s + k);
+                        acc = acc + r * r;
+                    }
+                    verdict = (acc <= thr) ? 1 : -1;
+                }
+            }
         }
-        if (act) ++k;
-
-        // verdicts: a lane's candidate is known once all its c-1 terms are in
-        const bool fail = act && (!valid || (c <= k && !(acc <= thr)));
-        const bool done = act && (!valid || c <= k);
-        const uint64_t fm = ballot(fail) & gmask;
-        const uint64_t dm = ballot(done) & gmask;
+        const uint64_t fm = ballot(act && verdict < 0) & gmask;
+        const double S2last = __shfl(S2, leader + W - 1);
+        const double S1last = __shfl(S1, leader + W - 1);
         if (!act) continue;
-        const int f = fm ? (ffs64(fm) - leader) : -1;  // first failing candidate in the group
-        if (f >= 0 && c0 + f - 1 <= k) {
-            // every smaller candidate has finished and passed: piece length is
-            // the last accepted candidate
-            const int32_t L = c0 + f - 1;
-            const double tend = t[s + L];
+        if (fm) {
+            // the first rejected candidate ends the piece at the last accepted length
+            const int32_t L = c0 + (ffs64(fm) - leader) - 1;
+            const double tend = at(s + L);
             if (j == 0) {
                 if (!isfinite(tend)) set_status(status, kStNonFinite);
                 st_len[obase + np] = L;
@@ -214,17 +250,18 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
             ++np;
             s += L;
             ts = tend;
+            c0 = 2;
+            S2c = 0.0;
+            S1c = 0.0;
             if (s >= e) {
                 if (j == 0) dom_count[dom] = np;
                 dom = -1;
-            } else {
-                c0 = 2;
-                setup = true;
             }
-        } else if (fm == 0ull && dm == gmask) {
-            // all W candidates accepted: next round
+        } else {
+            // all W candidates accepted: the next round extends the sums
             c0 += W;
-            setup = true;
+            S2c = S2last;
+            S1c = S1last;
         }
     }
 }
@@ -315,18 +352,18 @@ int domain_table(const CompressWs &w, const int64_t *series_off, int64_t n_serie
                  bool want_queue, hipStream_t st) {
     const int64_t md = max_domains(n_series, total_points, D);
     const unsigned sb = (unsigned)((n_series + 255) / 256 > 0 ? (n_series + 255) / 256 : 1);
-    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(64), 0, st, w.status, w.q_head);
+    JB_LAUNCH(k_prepare, dim3(1), dim3(64), 0, st, w.status, w.q_head);
     JB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_series_domains, dim3(sb), dim3(256), 0, st, series_off, n_series, D, w.ndom, w.status);
+    JB_LAUNCH(k_series_domains, dim3(sb), dim3(256), 0, st, series_off, n_series, D, w.ndom, w.status);
     JB_LAUNCH_CHECK();
     int rc = scan_i32_to_i64(w.ndom, w.dom_off, nullptr, n_series, w.scan_ws, st);
     if (rc) return rc;
     if (want_queue) {
-        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((D + 2 + 255) / 256)), dim3(256), 0, st, w.len_hist,
+        JB_LAUNCH(k_zero_u64, dim3((unsigned)((D + 2 + 255) / 256)), dim3(256), 0, st, w.len_hist,
                            (int64_t)D + 2);
         JB_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_fill_domains, dim3(sb), dim3(256), 0, st, series_off, w.dom_off, n_series, D, w.doms,
+    JB_LAUNCH(k_fill_domains, dim3(sb), dim3(256), 0, st, series_off, w.dom_off, n_series, D, w.doms,
                        want_queue ? w.len_hist : nullptr);
     JB_LAUNCH_CHECK();
     if (want_queue) {
@@ -335,7 +372,7 @@ int domain_table(const CompressWs &w, const int64_t *series_off, int64_t n_serie
         if (rc) return rc;
         int64_t blocks = (md + 255) / 256;
         if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(k_queue_scatter, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, w.dom_off + n_series,
+        JB_LAUNCH(k_queue_scatter, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, w.dom_off + n_series,
                            md, D, reinterpret_cast<unsigned long long *>(w.bin_off), w.queue);
         JB_LAUNCH_CHECK();
     }
@@ -352,10 +389,10 @@ int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t 
     int cap = device_cu_count() * 16;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, n_dom_p, w.dom_count, w.dom_poff,
+    JB_LAUNCH(k_compact, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, n_dom_p, w.dom_count, w.dom_poff,
                        w.st_len, w.st_inc, len, inc);
     JB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_piece_off, dim3((unsigned)((n_series + 1 + 255) / 256)), dim3(256), 0, st, w.dom_off,
+    JB_LAUNCH(k_piece_off, dim3((unsigned)((n_series + 1 + 255) / 256)), dim3(256), 0, st, w.dom_off,
                        w.dom_poff, n_series, piece_off, n_pieces);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
@@ -364,8 +401,21 @@ int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t 
 template <int W>
 void launch_w(dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
               int64_t dbase, int64_t dend, double tol2, int32_t max_len) {
-    hipLaunchKernelGGL((k_compress<W>), g, b, 0, st, t, w.doms, w.queue, n_dom_p, w.q_head, dbase, dend, tol2,
+    const size_t lds = compress_lds_per_wave<W>() * (b.x / kWave);
+    JB_LAUNCH((k_compress<W>), g, b, lds, st, t, w.doms, w.queue, n_dom_p, w.q_head, dbase, dend, tol2,
                        max_len, w.st_len, w.st_inc, w.dom_count, w.status);
+}
+
+size_t lds_per_wave(int W) {
+    switch (W) {
+        case 1: return compress_lds_per_wave<1>();
+        case 2: return compress_lds_per_wave<2>();
+        case 4: return compress_lds_per_wave<4>();
+        case 8: return compress_lds_per_wave<8>();
+        case 16: return compress_lds_per_wave<16>();
+        case 32: return compress_lds_per_wave<32>();
+        default: return compress_lds_per_wave<64>();
+    }
 }
 
 int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
@@ -419,6 +469,9 @@ extern "C" int jabba_compress(const double *values, const int64_t *series_off, i
     }
     if (wpb < 1 || wpb > 16 || bpc < 1 || bpc > 32) return JABBA_EINVAL;
     if (W != 1 && W != 2 && W != 4 && W != 8 && W != 16 && W != 32 && W != 64) return JABBA_EINVAL;
+    // a workgroup's ring buffers stay within 64 KB of LDS
+    const int max_wpb = (int)(65536 / lds_per_wave(W));
+    if (wpb > max_wpb) wpb = max_wpb < 1 ? 1 : max_wpb;
     rc = domain_table(w, series_off, n_series, total_points, D, true, st);
     if (rc) return rc;
     const int64_t *n_dom_p = w.dom_off + n_series;

@@ -521,7 +521,7 @@ int tree_sum_levels(const DigWs &w, int64_t N, double *level0, hipStream_t st, d
     while (m > 1) {
         const int64_t blocks = (m + kTreeLeaves - 1) / kTreeLeaves;
         double *out = w.tree[which];
-        hipLaunchKernelGGL(k_sum_level, dim3((unsigned)blocks), dim3(256), 0, st, in, w.ds, level, out);
+        JB_LAUNCH(k_sum_level, dim3((unsigned)blocks), dim3(256), 0, st, in, w.ds, level, out);
         JB_LAUNCH_CHECK();
         in = out;
         which ^= 1;
@@ -565,62 +565,84 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     if (s1w < 1 || s1w > 16) return JABBA_EINVAL;
     const double a2 = alpha * alpha;
 
-    hipLaunchKernelGGL(k_dig_prepare, dim3(1), dim3(64), 0, st, w.ds, n_pieces, max_pieces);
+    JB_LAUNCH(k_dig_prepare, dim3(1), dim3(64), 0, st, w.ds, n_pieces, max_pieces);
     JB_LAUNCH_CHECK();
     // scaling: two pairwise-sum passes over inc, exact integer sums of len
     const int64_t t0 = (N + kTreeLeaves - 1) / kTreeLeaves;
-    hipLaunchKernelGGL((k_sum_leaves<1>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0]);
+    JB_LAUNCH((k_sum_leaves<1>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0]);
     JB_LAUNCH_CHECK();
     double *tot = nullptr;
     int rc = tree_sum_levels(w, N, w.tree[0], st, &tot);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_mean, dim3(1), dim3(64), 0, st, w.ds, tot);
+    JB_LAUNCH(k_mean, dim3(1), dim3(64), 0, st, w.ds, tot);
     JB_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sum_leaves<2>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0]);
+    JB_LAUNCH((k_sum_leaves<2>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0]);
     JB_LAUNCH_CHECK();
     rc = tree_sum_levels(w, N, w.tree[0], st, &tot);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_sigma, dim3(1), dim3(64), 0, st, w.ds, tot, scl, alpha, dict->params);
+    JB_LAUNCH(k_sigma, dim3(1), dim3(64), 0, st, w.ds, tot, scl, alpha, dict->params);
     JB_LAUNCH_CHECK();
 
     // key and global sorting index
     rc = radix_sort_init(w.sb, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_key, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH(k_key, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0], w.sb.vals[0]);
     JB_LAUNCH_CHECK();
     const int64_t *n_live = &w.ds->n;
     rc = radix_global_hist(w.sb, n_live, N, st);
     if (rc) return rc;
     rc = radix_sort_pairs(w.sb, n_live, N, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0],
+    JB_LAUNCH(k_gather, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0],
                        w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
     JB_LAUNCH_CHECK();
 
     // Stage I
-    hipLaunchKernelGGL(k_cuts, dim3(grid_for(nblk + 1)), dim3(256), 0, st, w.sk, w.ds, (int64_t)B, nblk, w.cuts);
+    JB_LAUNCH(k_cuts, dim3(grid_for(nblk + 1)), dim3(256), 0, st, w.sk, w.ds, (int64_t)B, nblk, w.cuts);
     JB_LAUNCH_CHECK();
     const size_t lds = (size_t)s1w * kLdsBitWords * sizeof(uint64_t);
-    hipLaunchKernelGGL(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk,
+    JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk,
                        w.sk, w.sx, w.sy, w.slen, w.sinc, alpha, a2, w.gbits, w.lab, w.flag, w.pcnt, w.plen, w.pinc);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.flag, w.sidx, n_live, N, w.scan_ws, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_compact_starts, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.flag, w.sidx, w.sk, w.sx, w.sy,
+    JB_LAUNCH(k_compact_starts, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.flag, w.sidx, w.sk, w.sx, w.sy,
                        w.pcnt, w.plen, w.pinc, w.gk, w.gx, w.gy, w.gcnt, w.glen, w.ginc, w.g_count);
     JB_LAUNCH_CHECK();
 
     // Stage II over the starting points, then numbering of global groups
-    hipLaunchKernelGGL(k_stage2, dim3(1), dim3(64), 0, st, w.g_count, w.gk, w.gx, w.gy, w.gcnt, w.glen, w.ginc, alpha,
+    JB_LAUNCH(k_stage2, dim3(1), dim3(64), 0, st, w.g_count, w.gk, w.gx, w.gy, w.gcnt, w.glen, w.ginc, alpha,
                        a2, w.gbits, w.glab, w.gflag, w.ocnt, w.olen, w.oinc);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen,
+    JB_LAUNCH(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen,
                        w.oinc, w.ds, scl, *dict);
     JB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym,
+    JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym,
                        symbols);
     JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
+
+extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream,
+                                    int64_t *stats) {
+    if (!workspace || !stats || max_pieces < 0 || B < 1) return JABBA_EINVAL;
+    const DigWs w = carve_digitize(const_cast<void *>(workspace), max_pieces, B);
+    JB_HIP(hipStreamSynchronize((hipStream_t)stream));
+    DigState ds;
+    int64_t G = 0;
+    int32_t ctl[9] = {0};
+    JB_HIP(hipMemcpy(&ds, w.ds, sizeof(DigState), hipMemcpyDeviceToHost));
+    JB_HIP(hipMemcpy(&G, w.g_count, sizeof(int64_t), hipMemcpyDeviceToHost));
+    JB_HIP(hipMemcpy(ctl, w.sb.ctl, sizeof(ctl), hipMemcpyDeviceToHost));
+    uint32_t k = 0;
+    if (G > 0) JB_HIP(hipMemcpy(&k, w.gsym + G, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t active = 0;
+    for (int d = 0; d < 8; ++d) active += ctl[1 + d] ? 0 : 1;
+    stats[0] = ds.n;
+    stats[1] = G;
+    stats[2] = k;
+    stats[3] = active;
     return JABBA_OK;
 }

@@ -72,7 +72,7 @@ extern "C" int jabba_encode(const int32_t *len, const double *inc, const int64_t
     int64_t blocks = (max_pieces + kThreads - 1) / kThreads;
     const int64_t cap = (int64_t)device_cu_count() * 8;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(k_encode, dim3((unsigned)blocks), dim3(kThreads), 0, (hipStream_t)stream, len, inc, n_pieces,
+    JB_LAUNCH(k_encode, dim3((unsigned)blocks), dim3(kThreads), 0, (hipStream_t)stream, len, inc, n_pieces,
                        max_pieces, dict->params, dict->k, dict->capacity, dict->cx, dict->cy, symbols);
     JB_LAUNCH_CHECK();
     return JABBA_OK;

@@ -233,10 +233,10 @@ int sizes(const Src &src, const int64_t *piece_off, const int64_t *series_off, i
     const ReconWs w0 = carve_recon(nullptr, n_series);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
     const ReconWs w = carve_recon(workspace, n_series);
-    hipLaunchKernelGGL(k_recon_prep, dim3(1), dim3(64), 0, st, w.status);
+    JB_LAUNCH(k_recon_prep, dim3(1), dim3(64), 0, st, w.status);
     JB_LAUNCH_CHECK();
     if (n_series > 0) {
-        hipLaunchKernelGGL(k_recon_count, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, series_off,
+        JB_LAUNCH(k_recon_count, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, series_off,
                            n_series, w.cnt, w.status);
         JB_LAUNCH_CHECK();
     }
@@ -271,12 +271,12 @@ extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_of
     if (!t0 || !out || !series_off) return JABBA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
-    hipLaunchKernelGGL(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
+    JB_LAUNCH(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
                        out, lhat);
     JB_LAUNCH_CHECK();
     if (values) {
         if (!sse || !cnt) return JABBA_EINVAL;
-        hipLaunchKernelGGL(k_recon_sse, dim3(waves_grid(n_series)), dim3(256), 0, st, out_off, series_off, n_series,
+        JB_LAUNCH(k_recon_sse, dim3(waves_grid(n_series)), dim3(256), 0, st, out_off, series_off, n_series,
                            values, out, sse, cnt);
         JB_LAUNCH_CHECK();
     }
@@ -292,7 +292,7 @@ extern "C" int jabba_reconstruct_pieces(const int32_t *len, const double *inc, c
     int rc = sizes(src, piece_off, series_off, n_series, out_off, workspace, workspace_bytes, st);
     if (rc || n_series == 0) return rc;
     if (!t0 || !out) return JABBA_EINVAL;
-    hipLaunchKernelGGL(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
+    JB_LAUNCH(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
                        out, (int64_t *)nullptr);
     JB_LAUNCH_CHECK();
     return JABBA_OK;

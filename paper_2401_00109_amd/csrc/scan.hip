@@ -137,12 +137,12 @@ int scan_impl(const Tin *in, Tout *out, const int64_t *n_dev, int64_t n_max, voi
     Carve c(ws);
     Tout *sums = c.take<Tout>(tiles);
     Tout *grand = c.take<Tout>(1);
-    hipLaunchKernelGGL((k_tile_sums<Tin, Tout>), dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, sums, n_dev,
+    JB_LAUNCH((k_tile_sums<Tin, Tout>), dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, sums, n_dev,
                        n_max);
     JB_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_scan_sums<Tout>), dim3(1), dim3(1024), 0, st, sums, tiles, grand);
+    JB_LAUNCH((k_scan_sums<Tout>), dim3(1), dim3(1024), 0, st, sums, tiles, grand);
     JB_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_tile_scan<Tin, Tout>), dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, out, sums,
+    JB_LAUNCH((k_tile_scan<Tin, Tout>), dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, out, sums,
                        n_dev, n_max, grand);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
@@ -159,7 +159,7 @@ int fill_impl(T *p, T v, int64_t n, hipStream_t st) {
     if (n <= 0) return JABBA_OK;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+    JB_LAUNCH((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }

@@ -163,7 +163,7 @@ size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b) {
 }
 
 int radix_sort_init(const SortBuffers &b, hipStream_t st) {
-    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, st, b.ctl, b.ghist);
+    JB_LAUNCH(k_sort_init, dim3(1), dim3(256), 0, st, b.ctl, b.ghist);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -173,7 +173,7 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
     int cap = device_cu_count() * 8;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_global_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, b.keys[0], n_dev, n_max,
+    JB_LAUNCH(k_global_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, b.keys[0], n_dev, n_max,
                        b.ghist);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
@@ -181,19 +181,19 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
 
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st) {
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(512), 0, st, b.ghist, n_dev, n_max, b.ctl);
+    JB_LAUNCH(k_plan, dim3(1), dim3(512), 0, st, b.ghist, n_dev, n_max, b.ctl);
     JB_LAUNCH_CHECK();
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_tile_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], n_dev,
+        JB_LAUNCH(k_tile_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], n_dev,
                            n_max, tiles, shift, b.ctl, pass, b.hist);
         JB_LAUNCH_CHECK();
         int rc = scan_u32_to_u32(b.hist, b.hist, nullptr, 256 * tiles, b.scan_ws, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0],
+        JB_LAUNCH(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0],
                            b.vals[1], n_dev, n_max, tiles, shift, b.ctl, pass, b.hist);
         JB_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, st, b.ctl, pass);
+        JB_LAUNCH(k_flip, dim3(1), dim3(64), 0, st, b.ctl, pass);
         JB_LAUNCH_CHECK();
     }
     return JABBA_OK;

@@ -56,7 +56,9 @@ def gpu_digitize(ln, inc, alpha, scl=1.0, B=4096, capacity=None, tuning=None, ma
     sym, d, ws = J.digitize(L, I, npc, mp, alpha, scl, B, capacity=capacity, tuning=tuning)
     T.cuda.synchronize()
     st = J.workspace_status(ws)
-    return sym[:n].cpu().numpy(), d.host(), st
+    h = d.host()
+    h["stats"] = J.api.digitize_stats(ws, mp, B)
+    return sym[:n].cpu().numpy(), h, st
 
 
 def assert_centers_close(got, ora, inc, symbols, rel=1e-12):

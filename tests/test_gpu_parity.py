@@ -158,6 +158,7 @@ def test_digitize_parity(wid, B):
     od = O.digitize(ol, oi, w.alpha, w.scl, B)
     assert d["sigma_len"] == od.sigma_len and d["sigma_inc"] == od.sigma_inc
     assert d["k"] == od.k
+    assert d["stats"]["G"] == od.n_starts and d["stats"]["N"] == ol.size and d["stats"]["k"] == od.k
     np.testing.assert_array_equal(sym, od.symbols)
     np.testing.assert_array_equal(d["count"], od.count)
     np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
