@@ -170,8 +170,9 @@ def main() -> int:
     k = sz.dictionary.size()
     stats = sz.stats()
     G, active_passes = stats["G"], stats["sort_passes"]
+    groups2 = stats["stage2_groups"]
     log(f"N={N} pieces, G={G} starting points, k={k} symbols, {active_passes} radix passes, "
-        f"reconstruction MSE={rec.mse():.4e}")
+        f"{groups2} Stage II groups, reconstruction MSE={rec.mse():.4e}")
 
     # ---------------------------------------------------------------- timed region
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -294,6 +295,7 @@ def main() -> int:
                                f"(3-way random walk / sinusoid / piecewise-linear mix), {w.D}-interval domains, "
                                f"tol={w.tol}, alpha={w.alpha}, B={w.B}",
                    "points": w.n_points, "pieces": N, "symbols": k, "starting_points": G,
+                   "stage2_groups": groups2,
                    "step": "compress+digitize+encode(resident k=%d)+reconstruct" % resident.size()},
         "symbolize_points_per_s": round(w.n_points / (ms_sym / 1e3), 1),
         "symbolize_ms": round(ms_sym, 4),

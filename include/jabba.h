@@ -200,18 +200,27 @@ int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_piece
  * Counters of the last jabba_digitize that used `workspace` (same max_pieces
  * and B): stats[0] = N pieces, stats[1] = G Stage I starting points,
  * stats[2] = k symbols, stats[3] = radix passes that moved data (digits that
- * are equal in every key are skipped).  Synchronises `stream`.
+ * are equal in every key are skipped), stats[4] = number of independent groups
+ * Stage II ran on.  stats holds 5 entries.
+ * Synchronises `stream`.
  */
 int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream, int64_t *stats);
+
+/* Workspace bytes for jabba_encode with a dictionary of this capacity. */
+int jabba_encode_workspace(int64_t capacity, size_t *bytes);
 
 /*
  * Nearest-center digitization against an existing dictionary (Sec. 3.2,
  * c* = argmin_c ||p - c||, f_d = I_d(c*)): x = params[2]*(len/params[0]),
  * y = inc/params[1], symbol = argmin_c (x - cx_c)^2 + (y - cy_c)^2 over all
- * k symbols, ties to the lowest symbol.  symbols[max_pieces]: out.
+ * k symbols (each distance rounded as written), ties to the lowest symbol; -1
+ * when the dictionary is empty.  The centers are ordered by cx in the
+ * workspace and every piece walks outward from its x until the remaining
+ * centers are provably farther, which returns the same symbol as a full scan.
+ * symbols[max_pieces]: out.
  */
 int jabba_encode(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
-                 const jabba_dict *dict, int32_t *symbols, void *stream);
+                 const jabba_dict *dict, int32_t *symbols, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Inverse symbolization (Sec. 3.3).                                          */

@@ -24,7 +24,7 @@ JABBA_ENODEV = -7
 
 EXPORTS = [
     "jabba_abi_version", "jabba_status_str", "jabba_compress_workspace", "jabba_compress", "jabba_compress_plain",
-    "jabba_digitize_workspace", "jabba_digitize", "jabba_encode", "jabba_reconstruct_workspace",
+    "jabba_digitize_workspace", "jabba_digitize", "jabba_encode_workspace", "jabba_encode", "jabba_reconstruct_workspace",
     "jabba_reconstruct_size", "jabba_reconstruct", "jabba_reconstruct_pieces", "jabba_workspace_status",
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
@@ -86,7 +86,8 @@ def lib() -> C.CDLL:
             L.jabba_compress_plain.argtypes = [P, P, P, I64, I32, D, I32, P, P, P, P, P, SZ, P]
             L.jabba_digitize_workspace.argtypes = [I64, I32, C.POINTER(SZ)]
             L.jabba_digitize.argtypes = [P, P, P, I64, D, D, I32, C.POINTER(Tuning), P, C.POINTER(Dict), P, SZ, P]
-            L.jabba_encode.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P]
+            L.jabba_encode_workspace.argtypes = [I64, C.POINTER(SZ)]
+            L.jabba_encode.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
             L.jabba_reconstruct_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_reconstruct_size.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
             L.jabba_reconstruct.argtypes = [P, P, P, I64, P, C.POINTER(Dict), P, P, P, P, P, P, P]

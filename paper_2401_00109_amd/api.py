@@ -119,6 +119,12 @@ class Dictionary:
     def size(self) -> int:
         return int(self.k.item())
 
+    def encode_workspace(self) -> torch.Tensor:
+        """Scratch the encoder orders the centers in (allocated once per dictionary)."""
+        if getattr(self, "_enc_ws", None) is None:
+            self._enc_ws = _ws(encode_workspace_bytes(self.capacity), self.params.device)
+        return self._enc_ws
+
     def host(self) -> dict:
         k = min(self.size(), self.capacity)
         p = self.params.cpu().numpy()
@@ -157,10 +163,10 @@ class Dictionary:
 
 def digitize_stats(workspace: torch.Tensor, max_pieces: int, B: int, stream=None) -> dict:
     """N, G (Stage I starting points), k and active radix passes of the last digitize on this workspace."""
-    arr = (C.c_int64 * 4)()
+    arr = (C.c_int64 * 5)()
     L.check(L.lib().jabba_digitize_stats(_p(workspace), int(max_pieces), int(B), _stream(stream), arr),
             "jabba_digitize_stats")
-    return {"N": arr[0], "G": arr[1], "k": arr[2], "sort_passes": arr[3]}
+    return {"N": arr[0], "G": arr[1], "k": arr[2], "sort_passes": arr[3], "stage2_groups": arr[4]}
 
 
 def workspace_status(ws: torch.Tensor, stream=None) -> int:
@@ -236,14 +242,22 @@ def digitize(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, ma
     return symbols, dictionary, workspace
 
 
+def encode_workspace_bytes(capacity: int) -> int:
+    n = C.c_size_t()
+    L.check(L.lib().jabba_encode_workspace(int(capacity), C.byref(n)), "encode_workspace")
+    return n.value
+
+
 def encode(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, dictionary: Dictionary,
-           symbols: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+           symbols: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Nearest-center symbols against a resident dictionary (see jabba_encode)."""
     if symbols is None:
         symbols = torch.empty(max(max_pieces, 1), dtype=torch.int32, device=length.device)
+    if workspace is None:
+        workspace = dictionary.encode_workspace()
     d = dictionary.struct()
     rc = L.lib().jabba_encode(_p(length), _p(inc), _p(n_pieces), int(max_pieces), C.byref(d), _p(symbols),
-                              _stream(stream))
+                              _p(workspace), workspace.numel(), _stream(stream))
     L.check(rc, "jabba_encode")
     return symbols
 

@@ -49,30 +49,57 @@ __global__ void k_fill_domains(const int64_t *__restrict__ series_off, const int
                                int64_t n_series, int32_t D, Dom *__restrict__ doms,
                                unsigned long long *__restrict__ len_hist) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_series) return;
-    int64_t lo = series_off[s], n = series_off[s + 1] - series_off[s];
-    int64_t d0 = dom_off[s];
-    int64_t d = 0;
-    for (int64_t a = 0; a + 1 < n; a += D, ++d) {
-        int64_t b = a + D < n - 1 ? a + D : n - 1;
-        Dom x;
-        x.start = lo + a;
-        x.nint = (int32_t)(b - a);
-        x.series = (int32_t)s;
-        doms[d0 + d] = x;
-        if (len_hist) atomicAdd(&len_hist[D - x.nint], 1ull);
+    unsigned long long full = 0;
+    if (s < n_series) {
+        const int64_t lo = series_off[s], n = series_off[s + 1] - series_off[s];
+        const int64_t d0 = dom_off[s];
+        int64_t d = 0;
+        for (int64_t a = 0; a + 1 < n; a += D, ++d) {
+            const int64_t b = a + D < n - 1 ? a + D : n - 1;
+            Dom x;
+            x.start = lo + a;
+            x.nint = (int32_t)(b - a);
+            x.series = (int32_t)s;
+            doms[d0 + d] = x;
+            if (len_hist) {
+                if (x.nint == D)
+                    ++full;
+                else
+                    atomicAdd(&len_hist[D - x.nint], 1ull);
+            }
+        }
     }
+    // full-length domains all fall in bin 0: one atomic per wavefront
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) full += __shfl_xor(full, m);
+    if (len_hist && lane_id() == 0 && full) atomicAdd(&len_hist[0], full);
 }
 
 // queue position by descending length (counting sort; order inside a bin is
-// irrelevant to the results)
+// irrelevant to the results).  Lanes of a wavefront that share a bin take
+// their positions with one atomic.
 __global__ void k_queue_scatter(const Dom *__restrict__ doms, const int64_t *__restrict__ n_dom_p, int64_t max_dom,
                                 int32_t D, unsigned long long *__restrict__ cursor, int32_t *__restrict__ queue) {
-    int64_t n_dom = *n_dom_p;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_dom && i < max_dom;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long p = atomicAdd(&cursor[D - doms[i].nint], 1ull);
-        queue[p] = (int32_t)i;
+    const int64_t n_dom = *n_dom_p;
+    const int64_t lim = n_dom < max_dom ? n_dom : max_dom;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < lim; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool ok = i < lim;
+        const int bin = ok ? D - doms[i].nint : -1;
+        bool pending = ok;
+        while (__ballot(pending)) {
+            const int lead = __builtin_ctzll(__ballot(pending));
+            const int lb = __shfl(bin, lead);
+            const bool mine = pending && bin == lb;
+            const uint64_t m = __ballot(mine);
+            unsigned long long base = 0;
+            if (lane_id() == lead) base = atomicAdd(&cursor[lb], (unsigned long long)__popcll(m));
+            base = __shfl(base, lead);
+            if (mine) {
+                queue[base + __popcll(m & lanemask_lt())] = (int32_t)i;
+                pending = false;
+            }
+        }
     }
 }
 

@@ -22,7 +22,6 @@ namespace jabba {
 namespace {
 
 constexpr int kTreeLeaves = 1024;  // leaves per workgroup in the pairwise sums
-constexpr int kLdsBitWords = 1024; // 65,536 points per LDS bitmap
 
 __device__ __forceinline__ int64_t live(const int64_t *n_dev, int64_t n_max) {
     int64_t n = *n_dev;
@@ -66,7 +65,9 @@ __device__ __forceinline__ double block_tree_1024(double a0, double a1, double a
 // accumulates the exact integer sums of len and len^2.
 template <int Pass>
 __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ len, const double *__restrict__ inc,
-                                                    DigState *ds, double *__restrict__ out) {
+                                                    DigState *ds, double *__restrict__ out,
+                                                    unsigned long long *__restrict__ lpart) {
+    __shared__ unsigned long long ls[2][4];
     const int64_t n = ds->n;
     const int64_t base = (int64_t)blockIdx.x * kTreeLeaves + 4 * threadIdx.x;
     double a[4];
@@ -92,15 +93,50 @@ __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ 
     const double r = block_tree_1024(a[0], a[1], a[2], a[3]);
     if (threadIdx.x == 0) out[blockIdx.x] = r;
     if (Pass == 1) {
+        // exact integer partials per workgroup; reduced by k_sum_ints
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) {
             s1 += __shfl_xor(s1, m);
             s2 += __shfl_xor(s2, m);
         }
-        if (lane_id() == 0 && s1) {
-            atomicAdd(&ds->lsum[0], s1);
-            atomicAdd(&ds->lsum[1], s2);
+        if (lane_id() == 0) {
+            ls[0][threadIdx.x / kWave] = s1;
+            ls[1][threadIdx.x / kWave] = s2;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            lpart[2 * blockIdx.x] = ls[0][0] + ls[0][1] + ls[0][2] + ls[0][3];
+            lpart[2 * blockIdx.x + 1] = ls[1][0] + ls[1][1] + ls[1][2] + ls[1][3];
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sum_ints(const unsigned long long *__restrict__ lpart, int64_t nparts,
+                                                   DigState *ds) {
+    __shared__ unsigned long long ls[2][16];
+    unsigned long long s1 = 0, s2 = 0;
+    for (int64_t i = threadIdx.x; i < nparts; i += 1024) {
+        s1 += lpart[2 * i];
+        s2 += lpart[2 * i + 1];
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        s1 += __shfl_xor(s1, m);
+        s2 += __shfl_xor(s2, m);
+    }
+    if (lane_id() == 0) {
+        ls[0][threadIdx.x / kWave] = s1;
+        ls[1][threadIdx.x / kWave] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int wv = 0; wv < 16; ++wv) {
+            a += ls[0][wv];
+            b += ls[1][wv];
+        }
+        ds->lsum[0] = a;
+        ds->lsum[1] = b;
     }
 }
 
@@ -200,169 +236,317 @@ __global__ void k_cuts(const double *__restrict__ sk, const DigState *ds, int64_
 }
 
 // ------------------------------------------------------------ aggregation
-struct LdsBits {
-    uint64_t *w;
-    __device__ uint64_t load(int64_t i) const { return w[i]; }
-    __device__ void store(int64_t i, uint64_t v) const { w[i] = v; }
-    __device__ void orw(int64_t i, uint64_t m) const { w[i] |= m; }
-    __device__ void fence() const {}
+//
+// Pull form of the greedy aggregation.  Visiting presorted points in order,
+// the sequential greedy lets a start p claim every unassigned later q with
+// key_q - key_p <= alpha and (x_q - x_p)^2 + (y_q - y_p)^2 <= alpha^2.  So a
+// point belongs to the first (lowest-position) earlier start that covers it,
+// and is itself a start when no earlier start does.  The wavefront takes 64
+// consecutive points at a time: each lane tests its point against the active
+// starts (the earlier starts still within alpha in key, oldest first), then
+// the points no start covers are resolved among themselves lane by lane
+// (the first becomes a start, covers later lanes, and so on).  Both give the
+// sequential decisions exactly; the next 64 points are loaded while the
+// current ones are tested.
+
+constexpr int kActCap = 256;  // active starts cached in LDS per wavefront
+
+struct ActLds {
+    double k[kActCap];
+    double x[kActCap];
+    double y[kActCap];
+    int32_t p[kActCap];
 };
 
-struct GlobalBits {
-    uint64_t *w;
-    __device__ uint64_t load(int64_t i) const {
-        return __hip_atomic_load(&w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ void store(int64_t i, uint64_t v) const {
-        __hip_atomic_store(&w[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ void orw(int64_t i, uint64_t m) const {
-        __hip_atomic_fetch_or(&w[i], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ void fence() const { __threadfence(); }
-};
+// Active starts: an append-only list of positions in global memory (glist),
+// the newest kActCap of them mirrored in LDS with their coordinates.
+struct Active {
+    ActLds *c;
+    int32_t *glist;
+    int head, tail;
 
-// member weights: Stage I points weigh (1, len, inc); Stage II points are
-// Stage I groups and carry their partial sums
-struct PointWeights {
-    const int32_t *len;
-    const double *inc;
-    __device__ int64_t cnt(int64_t) const { return 1; }
-    __device__ int64_t ln(int64_t q) const { return len[q]; }
-    __device__ double ic(int64_t q) const { return inc[q]; }
-};
-struct GroupWeights {
-    const int64_t *c;
-    const int64_t *l;
-    const double *i;
-    __device__ int64_t cnt(int64_t q) const { return c[q]; }
-    __device__ int64_t ln(int64_t q) const { return l[q]; }
-    __device__ double ic(int64_t q) const { return i[q]; }
-};
-
-// Greedy aggregation of the presorted points [lo, hi) by one wavefront.
-// The wavefront scans a start's alpha-window 64 points at a time; the
-// assigned set is a bitmap (bit r = point lo + r).  lab[q] <- start position,
-// flag[q] <- 1 for starts, 0 for members; for every start p the partial sums
-// of its members: count and len exactly, inc as the start's value followed
-// by one pairwise wavefront sum per 64-point chunk, chunks in order.
-template <class Bits, class Wt>
-__device__ void aggregate_wave(int64_t lo, int64_t hi, const double *__restrict__ key, const double *__restrict__ x,
-                               const double *__restrict__ y, Wt wt, double alpha, double a2, Bits bits,
-                               int32_t *__restrict__ lab, uint32_t *__restrict__ flag, int64_t *__restrict__ ocnt,
-                               int64_t *__restrict__ olen, double *__restrict__ oinc) {
-    const int lane = lane_id();
-    const int64_t n = hi - lo;
-    const int64_t nw = (n + 63) >> 6;
-    for (int64_t i = lane; i < nw; i += kWave) {
-        uint64_t v = 0ull;
-        if (i == nw - 1 && (n & 63)) v = ~0ull << (n & 63);
-        bits.store(i, v);
+    __device__ void push(int32_t pos, double kp, double xp, double yp) {
+        if (lane_id() == 0) {
+            const int sl = tail % kActCap;
+            c->k[sl] = kp;
+            c->x[sl] = xp;
+            c->y[sl] = yp;
+            c->p[sl] = pos;
+            __hip_atomic_store(&glist[tail], pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++tail;
     }
-    bits.fence();
-    int64_t p = lo;
-    while (p < hi) {
-        const double kp = key[p], xp = x[p], yp = y[p];
-        int64_t cacc = wt.cnt(p), lacc = wt.ln(p);
-        double iacc = wt.ic(p);
-        if (lane == 0) {
-            lab[p] = (int32_t)p;
-            flag[p] = 1u;
-            bits.orw((p - lo) >> 6, 1ull << ((p - lo) & 63));
+    __device__ bool cached(int i) const { return tail - i <= kActCap; }
+    __device__ void get(int i, const double *key, const double *x, const double *y, double &kp, double &xp,
+                        double &yp, int32_t &pp) const {
+        if (cached(i)) {
+            const int sl = i % kActCap;
+            kp = c->k[sl];
+            xp = c->x[sl];
+            yp = c->y[sl];
+            pp = c->p[sl];
+        } else {
+            pp = __hip_atomic_load(&glist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            kp = key[pp];
+            xp = x[pp];
+            yp = y[pp];
         }
-        bits.fence();
-        for (int64_t q0 = p + 1; q0 < hi; q0 += kWave) {
-            const int64_t q = q0 + lane;
-            const bool inr = q < hi;
-            const double kq = inr ? key[q] : 0.0;
-            const bool inwin = inr && (kq - kp <= alpha);
-            bool claim = false;
-            if (inwin) {
-                const int64_t r = q - lo;
-                const bool taken = (bits.load(r >> 6) >> (r & 63)) & 1ull;
-                if (!taken) {
-                    const double dx = x[q] - xp;
-                    const double dy = y[q] - yp;
-                    const double dd = dx * dx;
-                    const double ee = dy * dy;
-                    claim = (dd + ee) <= a2;
-                }
-            }
-            const uint64_t cm = ballot(claim);
-            if (cm) {
-                if (claim) {
-                    lab[q] = (int32_t)p;
-                    flag[q] = 0u;
-                }
-                if (lane == 0) {
-                    const int64_t r0 = q0 - lo;
-                    const int sh = (int)(r0 & 63);
-                    bits.orw(r0 >> 6, cm << sh);
-                    if (sh) {
-                        const uint64_t hw = cm >> (64 - sh);
-                        if (hw) bits.orw((r0 >> 6) + 1, hw);
-                    }
-                }
-                bits.fence();
-                cacc += wave_sum_i64(claim ? wt.cnt(q) : 0);
-                lacc += wave_sum_i64(claim ? wt.ln(q) : 0);
-                iacc = iacc + wave_tree_sum(claim ? wt.ic(q) : 0.0);
-            }
-            if (ballot(inr && !inwin) != 0ull) break;
-        }
-        if (lane == 0) {
-            ocnt[p] = cacc;
-            olen[p] = lacc;
-            oinc[p] = iacc;
-        }
-        // next unassigned point after p
-        const int64_t from = p + 1 - lo;
-        p = hi;
-        for (int64_t w0 = from >> 6; w0 < nw; w0 += kWave) {
-            const int64_t wi = w0 + lane;
-            uint64_t v = wi < nw ? bits.load(wi) : ~0ull;
-            if (wi == (from >> 6) && (from & 63)) v |= ~0ull >> (64 - (from & 63));
-            const uint64_t fz = ballot(v != ~0ull);
-            if (fz) {
-                const int l = ffs64(fz);
-                const uint64_t vl = __shfl(v, l);
-                p = lo + ((w0 + l) << 6) + __builtin_ctzll(~vl);
+    }
+    // drop starts that no point with key >= k0 can reach
+    __device__ void expire(double k0, double alpha, const double *key) {
+        while (head < tail) {
+            double kh;
+            if (cached(head))
+                kh = c->k[head % kActCap];
+            else
+                kh = key[__hip_atomic_load(&glist[head], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)];
+            if (!(k0 - kh <= alpha))
+                ++head;
+            else
                 break;
+        }
+    }
+};
+
+__device__ __forceinline__ bool covers(double kq, double xq, double yq, double kp, double xp, double yp, double alpha,
+                                       double a2) {
+    if (!(kq - kp <= alpha)) return false;
+    const double dx = xq - xp;
+    const double dy = yq - yp;
+    const double dd = dx * dx;
+    const double ee = dy * dy;
+    return (dd + ee) <= a2;
+}
+
+// Runs the greedy over positions [from, to) with the active list A as the
+// state before `from`.  Owners are written to lab/flag when `write`.
+__device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__restrict__ key,
+                           const double *__restrict__ x, const double *__restrict__ y, double alpha, double a2,
+                           bool write, int32_t *__restrict__ lab, uint32_t *__restrict__ flag,
+                           int32_t *__restrict__ start_end = nullptr, int32_t range_end = 0) {
+    const int lane = lane_id();
+    double kn = 0.0, xn = 0.0, yn = 0.0;
+    if (from + lane < to) {
+        kn = key[from + lane];
+        xn = x[from + lane];
+        yn = y[from + lane];
+    }
+    for (int64_t b0 = from; b0 < to; b0 += kWave) {
+        const int64_t q = b0 + lane;
+        const bool inr = q < to;
+        const double kq = kn, xq = xn, yq = yn;
+        if (b0 + kWave + lane < to) {  // next batch, loaded while this one is tested
+            kn = key[b0 + kWave + lane];
+            xn = x[b0 + kWave + lane];
+            yn = y[b0 + kWave + lane];
+        }
+        A.expire(__shfl(kq, 0), alpha, key);
+        if (A.head < A.tail && !A.cached(A.head)) __threadfence();
+        int32_t owner = -1;
+        bool open = inr;
+        for (int i = A.head; i < A.tail; ++i) {
+            if (ballot(open) == 0ull) break;
+            double kp, xp, yp;
+            int32_t pp;
+            A.get(i, key, x, y, kp, xp, yp, pp);
+            if (open && covers(kq, xq, yq, kp, xp, yp, alpha, a2)) {
+                owner = pp;
+                open = false;
             }
+        }
+        uint64_t pend = ballot(open);
+        while (pend) {
+            const int l = ffs64(pend);
+            const double kl = __shfl(kq, l), xl = __shfl(xq, l), yl = __shfl(yq, l);
+            const int32_t pl = (int32_t)(b0 + l);
+            if (lane == l) {
+                owner = pl;
+                open = false;
+            } else if (open && lane > l && covers(kq, xq, yq, kl, xl, yl, alpha, a2)) {
+                owner = pl;
+                open = false;
+            }
+            A.push(pl, kl, xl, yl);
+            pend = ballot(open);
+        }
+        if (write && inr) {
+            lab[q] = owner;
+            flag[q] = owner == (int32_t)q ? 1u : 0u;
+            if (start_end && owner == (int32_t)q) start_end[q] = range_end;
         }
     }
 }
 
+// Stage I: one wavefront per block of sorted pieces.
 __global__ __launch_bounds__(1024) void k_stage1(const int64_t *__restrict__ cuts, int64_t nblk_max,
                                                  const double *__restrict__ sk, const double *__restrict__ sx,
-                                                 const double *__restrict__ sy, const int32_t *__restrict__ slen,
-                                                 const double *__restrict__ sinc, double alpha, double a2,
-                                                 uint64_t *__restrict__ gbits, int32_t *__restrict__ lab,
-                                                 uint32_t *__restrict__ flag, int64_t *__restrict__ pcnt,
-                                                 int64_t *__restrict__ plen, double *__restrict__ pinc) {
-    extern __shared__ uint64_t lds_bits[];
+                                                 const double *__restrict__ sy, double alpha, double a2,
+                                                 int32_t *__restrict__ glist, int32_t *__restrict__ lab,
+                                                 uint32_t *__restrict__ flag, int32_t *__restrict__ start_end) {
+    extern __shared__ ActLds act_lds[];
     const int wave = threadIdx.x / kWave;
     const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
     if (blk >= nblk_max) return;
     const int64_t lo = cuts[blk], hi = cuts[blk + 1];
     if (lo >= hi) return;
-    PointWeights wt{slen, sinc};
-    if (hi - lo <= (int64_t)kLdsBitWords * 64) {
-        LdsBits b{lds_bits + (size_t)wave * kLdsBitWords};
-        aggregate_wave(lo, hi, sk, sx, sy, wt, alpha, a2, b, lab, flag, pcnt, plen, pinc);
-    } else {
-        GlobalBits b{gbits + (lo >> 6) + blk};
-        aggregate_wave(lo, hi, sk, sx, sy, wt, alpha, a2, b, lab, flag, pcnt, plen, pinc);
+    Active A{&act_lds[wave], glist + lo, 0, 0};
+    pull_range(lo, hi, A, sk, sx, sy, alpha, a2, true, lab, flag, start_end, (int32_t)hi);
+}
+
+// Stage II runs on independent groups of starting points.  Two starting
+// points can only interact when their keys are within alpha and their x
+// within alpha.  x = scl*len/sigma_len grows with len, so when one length step
+// already separates x by more than alpha (checked with a margin that covers
+// rounding) the points of each length form their own column; otherwise all
+// points share one column.  Inside a column, ordered by position (= key
+// order), a key gap larger than alpha cuts the chain: no point before it can
+// reach a point after it (FP subtraction is monotone).  The greedy of every
+// resulting group, run in position order, makes exactly the decisions of the
+// greedy over all starting points.
+constexpr int64_t kLenCap = (int64_t)1 << 30;
+
+__global__ void k_col_keys(const int64_t *__restrict__ g_count, const int32_t *__restrict__ spos,
+                           const int32_t *__restrict__ slen, const DigState *ds, double scl, double a2,
+                           uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t G = *g_count;
+    const double step = scl / ds->sigma_len;
+    const bool sep = step * step > a2 * (1.0 + 1e-9);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t col = 0;
+        if (sep) {
+            col = slen[spos[g]];
+            if (col > kLenCap) col = kLenCap;
+        }
+        keys[g] = ((uint64_t)col << 32) | (uint64_t)g;
+        vals[g] = (uint32_t)g;
+    }
+}
+
+// group cut flags over the column-sorted order, and the gathered coordinates
+__global__ void k_col_cuts(const int64_t *__restrict__ g_count, const uint64_t *__restrict__ k0,
+                           const uint64_t *__restrict__ k1, const int32_t *__restrict__ ctl,
+                           const double *__restrict__ gk, const double *__restrict__ gx, const double *__restrict__ gy,
+                           double alpha, uint32_t *__restrict__ cut, int32_t *__restrict__ ord,
+                           double *__restrict__ ck, double *__restrict__ cx, double *__restrict__ cy) {
+    const int64_t G = *g_count;
+    const uint64_t *keys = ctl[0] ? k1 : k0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t kj = keys[j];
+        const int32_t g = (int32_t)(kj & 0xffffffffull);
+        bool c = j == 0;
+        if (!c) {
+            const uint64_t kp = keys[j - 1];
+            const int32_t gp = (int32_t)(kp & 0xffffffffull);
+            c = (kj >> 32) != (kp >> 32) || !(gk[g] - gk[gp] <= alpha);
+        }
+        cut[j] = c ? 1u : 0u;
+        ord[j] = g;
+        ck[j] = gk[g];
+        cx[j] = gx[g];
+        cy[j] = gy[g];
+    }
+}
+
+// group start positions (in the column-sorted order) from the cut flags
+__global__ void k_col_groups(const int64_t *__restrict__ g_count, const uint32_t *__restrict__ cut,
+                             const uint32_t *__restrict__ gid, int32_t *__restrict__ gstart,
+                             int64_t *__restrict__ n_groups) {
+    const int64_t G = *g_count;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t ng = G > 0 ? (int64_t)gid[G] : 0;
+        *n_groups = ng;
+        gstart[ng] = (int32_t)G;
+    }
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += (int64_t)gridDim.x * blockDim.x)
+        if (cut[j]) gstart[gid[j]] = (int32_t)j;
+}
+
+// one wavefront per group; owners are written back in starting-point positions
+__global__ __launch_bounds__(256) void k_col_greedy(const int64_t *__restrict__ n_groups_p,
+                                                    const int32_t *__restrict__ gstart, const int32_t *__restrict__ ord,
+                                                    const double *__restrict__ ck, const double *__restrict__ cx,
+                                                    const double *__restrict__ cy, double alpha, double a2,
+                                                    int32_t *__restrict__ glist, int32_t *__restrict__ own,
+                                                    uint32_t *__restrict__ oflag, int32_t *__restrict__ glab,
+                                                    uint32_t *__restrict__ gflag) {
+    extern __shared__ ActLds act_lds[];
+    const int wave = threadIdx.x / kWave;
+    const int64_t ng = *n_groups_p;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave; gi < ng; gi += waves) {
+        const int64_t lo = gstart[gi], hi = gstart[gi + 1];
+        Active A{&act_lds[wave], glist + lo, 0, 0};
+        pull_range(lo, hi, A, ck, cx, cy, alpha, a2, true, own, oflag);
+        __threadfence();  // owners written by other lanes are read back below
+        for (int64_t j = lo + lane_id(); j < hi; j += kWave) {
+            const int32_t g = ord[j];
+            glab[g] = ord[own[j]];
+            gflag[g] = oflag[j];
+        }
+    }
+}
+
+// Per-start sums over the start's members (lab == start), in position order:
+// one pairwise wavefront sum per 64 positions, chunks added in order.  The
+// members of a start lie in its alpha-window of keys after it.
+template <bool Points>
+__global__ __launch_bounds__(256) void k_group_sums(const int64_t *__restrict__ n_starts_p, int64_t n_pos_max,
+                                                    const int64_t *__restrict__ n_pos_p,
+                                                    const int32_t *__restrict__ start_pos,
+                                                    const int32_t *__restrict__ start_end,
+                                                    const uint32_t *__restrict__ flag, const double *__restrict__ key,
+                                                    const int32_t *__restrict__ lab, const int32_t *__restrict__ wlen32,
+                                                    const int64_t *__restrict__ wcnt, const int64_t *__restrict__ wlen,
+                                                    const double *__restrict__ winc, double alpha,
+                                                    int64_t *__restrict__ ocnt, int64_t *__restrict__ olen,
+                                                    double *__restrict__ oinc) {
+    const int lane = lane_id();
+    const int64_t n_starts = *n_starts_p;
+    int64_t n_pos = *n_pos_p;
+    if (n_pos > n_pos_max) n_pos = n_pos_max;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < n_starts; g += waves) {
+        int64_t p, pend = n_pos;
+        if (Points) {
+            p = start_pos[g];
+            pend = start_end[p];  // members never leave the start's block
+        } else {
+            if (!flag[g]) continue;
+            p = g;
+        }
+        const double kp = key[p];
+        int64_t c = 0, l = 0;
+        double ic = 0.0;
+        for (int64_t q0 = p; q0 < pend; q0 += kWave) {
+            const int64_t q = q0 + lane;
+            const bool inr = q < pend;
+            const bool inwin = inr && (key[q] - kp <= alpha);
+            const bool mem = inwin && lab[q] == (int32_t)p;
+            int64_t cq = 0, lq = 0;
+            double iq = 0.0;
+            if (mem) {
+                cq = Points ? 1 : wcnt[q];
+                lq = Points ? (int64_t)wlen32[q] : wlen[q];
+                iq = winc[q];
+            }
+            c += wave_sum_i64(cq);
+            l += wave_sum_i64(lq);
+            ic = ic + wave_tree_sum(iq);
+            if (ballot(inr && !inwin) != 0ull) break;
+        }
+        if (lane == 0) {
+            ocnt[g] = c;
+            olen[g] = l;
+            oinc[g] = ic;
+        }
     }
 }
 
 __global__ void k_compact_starts(const DigState *ds, const uint32_t *__restrict__ flag,
                                  const uint32_t *__restrict__ sidx, const double *__restrict__ sk,
                                  const double *__restrict__ sx, const double *__restrict__ sy,
-                                 const int64_t *__restrict__ pcnt, const int64_t *__restrict__ plen,
-                                 const double *__restrict__ pinc, double *__restrict__ gk, double *__restrict__ gx,
-                                 double *__restrict__ gy, int64_t *__restrict__ gcnt, int64_t *__restrict__ glen,
-                                 double *__restrict__ ginc, int64_t *__restrict__ g_count) {
+                                 double *__restrict__ gk, double *__restrict__ gx, double *__restrict__ gy,
+                                 int32_t *__restrict__ spos, int64_t *__restrict__ g_count) {
     const int64_t n = ds->n;
     if (blockIdx.x == 0 && threadIdx.x == 0) *g_count = (int64_t)sidx[n];
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -371,29 +555,7 @@ __global__ void k_compact_starts(const DigState *ds, const uint32_t *__restrict_
         gk[g] = sk[p];
         gx[g] = sx[p];
         gy[g] = sy[p];
-        gcnt[g] = pcnt[p];
-        glen[g] = plen[p];
-        ginc[g] = pinc[p];
-    }
-}
-
-__global__ __launch_bounds__(64) void k_stage2(const int64_t *__restrict__ g_count, const double *__restrict__ gk,
-                                               const double *__restrict__ gx, const double *__restrict__ gy,
-                                               const int64_t *__restrict__ gcnt, const int64_t *__restrict__ glen,
-                                               const double *__restrict__ ginc, double alpha, double a2,
-                                               uint64_t *__restrict__ gbits, int32_t *__restrict__ glab,
-                                               uint32_t *__restrict__ gflag, int64_t *__restrict__ ocnt,
-                                               int64_t *__restrict__ olen, double *__restrict__ oinc) {
-    __shared__ uint64_t lds_bits[kLdsBitWords];
-    const int64_t G = *g_count;
-    if (G <= 0) return;
-    GroupWeights wt{gcnt, glen, ginc};
-    if (G <= (int64_t)kLdsBitWords * 64) {
-        LdsBits b{lds_bits};
-        aggregate_wave((int64_t)0, G, gk, gx, gy, wt, alpha, a2, b, glab, gflag, ocnt, olen, oinc);
-    } else {
-        GlobalBits b{gbits};
-        aggregate_wave((int64_t)0, G, gk, gx, gy, wt, alpha, a2, b, glab, gflag, ocnt, olen, oinc);
+        spos[g] = (int32_t)p;
     }
 }
 
@@ -436,6 +598,7 @@ __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, c
 struct DigWs {
     DigState *ds;
     double *tree[2];
+    unsigned long long *lpart;
     SortBuffers sb;
     double *sk, *sx, *sy, *sinc;
     int32_t *slen;
@@ -444,17 +607,25 @@ struct DigWs {
     int32_t *lab;
     uint32_t *flag;
     uint32_t *sidx;
-    int64_t *pcnt, *plen;
-    double *pinc;
+    int32_t *glist;
     double *gk, *gx, *gy, *ginc;
     int64_t *gcnt, *glen;
+    int32_t *spos;
     int64_t *g_count;
     int32_t *glab;
     uint32_t *gflag;
     uint32_t *gsym;
     int64_t *ocnt, *olen;
     double *oinc;
-    uint64_t *gbits;
+    uint32_t *cut;
+    uint32_t *cgid;
+    int32_t *ord;
+    int32_t *gstart;
+    int64_t *n_groups;
+    double *ck, *cx, *cy;
+    int32_t *own;
+    uint32_t *oflag;
+    int32_t *send;
     void *scan_ws;
     size_t bytes;
 };
@@ -470,6 +641,7 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     const int64_t t0 = (N + kTreeLeaves - 1) / kTreeLeaves;
     w.tree[0] = c.take<double>(t0 + 1);
     w.tree[1] = c.take<double>((t0 + kTreeLeaves - 1) / kTreeLeaves + 1);
+    w.lpart = c.take<unsigned long long>(2 * t0 + 2);
     sort_workspace(N, c, &w.sb);
     w.sk = c.take<double>(N);
     w.sx = c.take<double>(N);
@@ -481,15 +653,14 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     w.lab = c.take<int32_t>(N);
     w.flag = c.take<uint32_t>(N);
     w.sidx = c.take<uint32_t>(N + 1);
-    w.pcnt = c.take<int64_t>(N);
-    w.plen = c.take<int64_t>(N);
-    w.pinc = c.take<double>(N);
+    w.glist = c.take<int32_t>(N + 64);
     w.gk = c.take<double>(N);
     w.gx = c.take<double>(N);
     w.gy = c.take<double>(N);
     w.ginc = c.take<double>(N);
     w.gcnt = c.take<int64_t>(N);
     w.glen = c.take<int64_t>(N);
+    w.spos = c.take<int32_t>(N);
     w.g_count = c.take<int64_t>(1);
     w.glab = c.take<int32_t>(N);
     w.gflag = c.take<uint32_t>(N);
@@ -497,7 +668,17 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     w.ocnt = c.take<int64_t>(N);
     w.olen = c.take<int64_t>(N);
     w.oinc = c.take<double>(N);
-    w.gbits = c.take<uint64_t>(N / 64 + nblk + 4);
+    w.cut = c.take<uint32_t>(N);
+    w.cgid = c.take<uint32_t>(N + 1);
+    w.ord = c.take<int32_t>(N);
+    w.gstart = c.take<int32_t>(N + 1);
+    w.n_groups = c.take<int64_t>(1);
+    w.ck = c.take<double>(N);
+    w.cx = c.take<double>(N);
+    w.cy = c.take<double>(N);
+    w.own = c.take<int32_t>(N);
+    w.oflag = c.take<uint32_t>(N);
+    w.send = c.take<int32_t>(N);
     w.scan_ws = c.take<char>(scan_workspace(N + 1));
     w.bytes = c.bytes();
     return w;
@@ -569,14 +750,16 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     JB_LAUNCH_CHECK();
     // scaling: two pairwise-sum passes over inc, exact integer sums of len
     const int64_t t0 = (N + kTreeLeaves - 1) / kTreeLeaves;
-    JB_LAUNCH((k_sum_leaves<1>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0]);
+    JB_LAUNCH((k_sum_leaves<1>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0], w.lpart);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_sum_ints, dim3(1), dim3(1024), 0, st, w.lpart, t0, w.ds);
     JB_LAUNCH_CHECK();
     double *tot = nullptr;
     int rc = tree_sum_levels(w, N, w.tree[0], st, &tot);
     if (rc) return rc;
     JB_LAUNCH(k_mean, dim3(1), dim3(64), 0, st, w.ds, tot);
     JB_LAUNCH_CHECK();
-    JB_LAUNCH((k_sum_leaves<2>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0]);
+    JB_LAUNCH((k_sum_leaves<2>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0], w.lpart);
     JB_LAUNCH_CHECK();
     rc = tree_sum_levels(w, N, w.tree[0], st, &tot);
     if (rc) return rc;
@@ -597,30 +780,55 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
                        w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
     JB_LAUNCH_CHECK();
 
-    // Stage I
+    // Stage I: blocks of B sorted pieces, one wavefront each
     JB_LAUNCH(k_cuts, dim3(grid_for(nblk + 1)), dim3(256), 0, st, w.sk, w.ds, (int64_t)B, nblk, w.cuts);
     JB_LAUNCH_CHECK();
-    const size_t lds = (size_t)s1w * kLdsBitWords * sizeof(uint64_t);
-    JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk,
-                       w.sk, w.sx, w.sy, w.slen, w.sinc, alpha, a2, w.gbits, w.lab, w.flag, w.pcnt, w.plen, w.pinc);
+    const size_t lds = (size_t)s1w * sizeof(ActLds);
+    JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk, w.sk,
+              w.sx, w.sy, alpha, a2, w.glist, w.lab, w.flag, w.send);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.flag, w.sidx, n_live, N, w.scan_ws, st);
     if (rc) return rc;
-    JB_LAUNCH(k_compact_starts, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.flag, w.sidx, w.sk, w.sx, w.sy,
-                       w.pcnt, w.plen, w.pinc, w.gk, w.gx, w.gy, w.gcnt, w.glen, w.ginc, w.g_count);
+    JB_LAUNCH(k_compact_starts, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.flag, w.sidx, w.sk, w.sx, w.sy, w.gk,
+              w.gx, w.gy, w.spos, w.g_count);
+    JB_LAUNCH_CHECK();
+    // partial sums of every local group, in position order
+    JB_LAUNCH((k_group_sums<true>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, n_live, w.spos,
+              w.send, w.flag, w.sk, w.lab, w.slen, (const int64_t *)nullptr, (const int64_t *)nullptr, w.sinc, alpha, w.gcnt,
+              w.glen, w.ginc);
     JB_LAUNCH_CHECK();
 
-    // Stage II over the starting points, then numbering of global groups
-    JB_LAUNCH(k_stage2, dim3(1), dim3(64), 0, st, w.g_count, w.gk, w.gx, w.gy, w.gcnt, w.glen, w.ginc, alpha,
-                       a2, w.gbits, w.glab, w.gflag, w.ocnt, w.olen, w.oinc);
+    // Stage II over the starting points: independent groups (length column,
+    // key gaps), one wavefront per group
+    rc = radix_sort_init(w.sb, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_col_keys, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.spos, w.slen, w.ds, scl, a2,
+              w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH_CHECK();
+    rc = radix_global_hist(w.sb, w.g_count, N, st);
+    if (rc) return rc;
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.ctl, w.gk,
+              w.gx, w.gy, alpha, w.cut, w.ord, w.ck, w.cx, w.cy);
+    JB_LAUNCH_CHECK();
+    rc = scan_u32_to_u32(w.cut, w.cgid, w.g_count, N, w.scan_ws, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_col_groups, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.cut, w.cgid, w.gstart, w.n_groups);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_col_greedy, dim3(grid_for(N * kWave / 4 + 1, 32)), dim3(4 * kWave), 4 * sizeof(ActLds), st,
+              w.n_groups, w.gstart, w.ord, w.ck, w.cx, w.cy, alpha, a2, w.glist, w.own, w.oflag, w.glab, w.gflag);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
-    JB_LAUNCH(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen,
-                       w.oinc, w.ds, scl, *dict);
+    JB_LAUNCH((k_group_sums<false>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, w.g_count,
+              (const int32_t *)nullptr, (const int32_t *)nullptr, w.gflag, w.gk, w.glab, (const int32_t *)nullptr, w.gcnt, w.glen, w.ginc,
+              alpha, w.ocnt, w.olen, w.oinc);
     JB_LAUNCH_CHECK();
-    JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym,
-                       symbols);
+    JB_LAUNCH(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen, w.oinc, w.ds,
+              scl, *dict);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, symbols);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -644,5 +852,8 @@ extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, i
     stats[1] = G;
     stats[2] = k;
     stats[3] = active;
+    int64_t ng = 0;
+    JB_HIP(hipMemcpy(&ng, w.n_groups, sizeof(int64_t), hipMemcpyDeviceToHost));
+    stats[4] = ng;
     return JABBA_OK;
 }

@@ -342,3 +342,43 @@ def test_full_size_scale_workload():
     np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
     worst = assert_centers_close(d, od, oi, od.symbols)
     say(f"  digitize parity ok: k={od.k} G={od.n_starts} center_inc worst rel {worst:.3e}")
+
+
+def _gpu_encode(ln, inc, sl, si, scl, cx, cy):
+    import paper_2401_00109_amd as J
+    T = torch()
+    k = len(cx)
+    d = J.Dictionary.from_host(sl, si, scl, 0.1, np.ones(k), np.zeros(k), cx, cy, device=DEV)
+    npc = T.tensor([len(ln)], dtype=T.int64, device=DEV)
+    sym = J.encode(to_dev(np.asarray(ln, np.int32)), to_dev(np.asarray(inc, np.float64)), npc, len(ln), d)
+    T.cuda.synchronize()
+    return sym[: len(ln)].cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [1, 2, 37, 4096, 4097, 20000])
+def test_encode_large_and_tied_dictionaries(k):
+    rng = np.random.default_rng(k)
+    # centers on discrete length columns with duplicated and mirrored points
+    cx = rng.integers(1, 30, k) * 0.37
+    cy = np.round(rng.standard_normal(k), 2)
+    if k > 10:
+        cx[k // 2:k // 2 + 5] = cx[0]
+        cy[k // 2:k // 2 + 5] = cy[0]  # exact duplicates: lowest id must win
+    ln = rng.integers(1, 30, 20000).astype(np.int32)
+    inc = np.round(rng.standard_normal(20000), 2) * 0.9
+    sl, si = 2.7027027027027026, 0.9
+    say(f"encode k={k}")
+    got = _gpu_encode(ln, inc, sl, si, 1.0, cx, cy)
+    exp = O.encode(ln, inc, sl, si, 1.0, cx, cy)
+    np.testing.assert_array_equal(got, exp)
+
+
+def test_encode_equidistant_ties():
+    # queries exactly halfway between two centers (dyadic values: exact distances)
+    cx = np.array([1.0, 1.0, 2.0, 0.0, 1.5])
+    cy = np.array([0.5, -0.5, 0.0, 0.0, 0.0])
+    ln = np.array([1, 1, 1, 1], np.int32)
+    inc = np.array([0.0, 0.25, -0.25, 0.5])
+    got = _gpu_encode(ln, inc, 1.0, 1.0, 1.0, cx, cy)
+    exp = O.encode(ln, inc, 1.0, 1.0, 1.0, cx, cy)
+    np.testing.assert_array_equal(got, exp)
