@@ -19,7 +19,6 @@ on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,6 +29,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2401_00109_amd.rocprof_summary import source_hash  # noqa: E402
+
 METRIC = "points symbolized/sec, batched vs per-domain launch; %HBM peak; p99 latency"
 HBM_PEAK_GBS = 8000.0
 WORKLOAD_IDS = {"tiny": 1, "scale": 2, "uneven": 3, "multivar": 4}
@@ -37,15 +38,6 @@ WORKLOAD_IDS = {"tiny": 1, "scale": 2, "uneven": 3, "multivar": 4}
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def source_hash() -> str:
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2401_00109_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
 
 
 # Algorithmic bytes each kernel must move per launch ("Kernels
@@ -89,9 +81,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale", choices=sorted(WORKLOAD_IDS))
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload's series (tests only)")
-    ap.add_argument("--cpu-sample-series", type=int, default=256)
+    ap.add_argument("--cpu-sample-series", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay (profiler runs)")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain 1 GiB copy kernel (for rocprofv3 counter scaling)")
     ap.add_argument("--tuning", default=None, help="JSON dict of jabba_tuning fields")
@@ -194,7 +187,7 @@ def main() -> int:
     torch.cuda.synchronize()
     ms_sym = ev0.elapsed_time(ev1) / args.steps
     plan = J.Plan(v, so, w.D, w.tol, w.alpha, w.scl, w.B, max_pieces=max(w.n_points, 1), capacity=max(N, 1),
-                  tuning=tuning) if w.n_points <= 200_000_000 else None
+                  tuning=tuning) if (w.n_points <= 200_000_000 and not args.no_graph) else None
     ms_graph = None
     if plan is not None:
         plan.run()

@@ -70,6 +70,12 @@ struct KernelTimer {
         ::jabba::KernelTimer jb_timer_(#kernel, st);                   \
         hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__); \
     } while (0)
+// Same, with an explicit timing name (kernels launched for several purposes).
+#define JB_LAUNCH_NAMED(name, kernel, grid, block, lds, st, ...)       \
+    do {                                                               \
+        ::jabba::KernelTimer jb_timer_(name, st);                      \
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__); \
+    } while (0)
 
 // ---------------------------------------------------------------- device side
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -153,6 +159,8 @@ int radix_sort_init(const SortBuffers &b, hipStream_t st);
 int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);
 // Sorts n (device count) pairs held in keys[0]/vals[0]; the result is in
 // keys[ctl[0]], vals[ctl[0]] (read on device by consumers).
-int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);
+// `tag` suffixes the timing names of the pass kernels ("" for the main sort).
+int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st,
+                     const char *tag = "");
 
 }  // namespace jabba

@@ -35,6 +35,7 @@ struct DigState {
     double sigma_len;
     double sigma_inc;
     int64_t n;  // live piece count (clamped)
+    int64_t sort_passes;  // radix passes of the main sort that moved data
 };
 
 __global__ void k_dig_prepare(DigState *ds, const int64_t *n_dev, int64_t n_max) {
@@ -195,7 +196,7 @@ __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict_
     }
 }
 
-__global__ void k_gather(const int32_t *__restrict__ len, const double *__restrict__ inc, const DigState *ds,
+__global__ void k_gather(const int32_t *__restrict__ len, const double *__restrict__ inc, DigState *ds,
                          double scl, const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
                          const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
                          double *__restrict__ sk, double *__restrict__ sx, double *__restrict__ sy,
@@ -204,6 +205,11 @@ __global__ void k_gather(const int32_t *__restrict__ len, const double *__restri
     const double sl = ds->sigma_len, si = ds->sigma_inc;
     const uint64_t *ks = ctl[0] ? k1 : k0;
     const uint32_t *vs = ctl[0] ? v1 : v0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t act = 0;
+        for (int d = 0; d < 8; ++d) act += ctl[1 + d] ? 0 : 1;
+        ds->sort_passes = act;
+    }
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t c = vs[p];
         const int32_t l = len[c];
@@ -807,7 +813,7 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     JB_LAUNCH_CHECK();
     rc = radix_global_hist(w.sb, w.g_count, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, w.g_count, N, st);
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups");
     if (rc) return rc;
     JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.ctl, w.gk,
               w.gx, w.gy, alpha, w.cut, w.ord, w.ck, w.cx, w.cy);
@@ -840,14 +846,11 @@ extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, i
     JB_HIP(hipStreamSynchronize((hipStream_t)stream));
     DigState ds;
     int64_t G = 0;
-    int32_t ctl[9] = {0};
     JB_HIP(hipMemcpy(&ds, w.ds, sizeof(DigState), hipMemcpyDeviceToHost));
     JB_HIP(hipMemcpy(&G, w.g_count, sizeof(int64_t), hipMemcpyDeviceToHost));
-    JB_HIP(hipMemcpy(ctl, w.sb.ctl, sizeof(ctl), hipMemcpyDeviceToHost));
     uint32_t k = 0;
     if (G > 0) JB_HIP(hipMemcpy(&k, w.gsym + G, sizeof(uint32_t), hipMemcpyDeviceToHost));
-    int64_t active = 0;
-    for (int d = 0; d < 8; ++d) active += ctl[1 + d] ? 0 : 1;
+    const int64_t active = ds.sort_passes;
     stats[0] = ds.n;
     stats[1] = G;
     stats[2] = k;

@@ -64,6 +64,7 @@ __global__ void k_plan(const uint32_t *__restrict__ ghist, const int64_t *n_dev,
     if (lane == 0) ctl[1 + d] = (m != 0ull || n <= 1) ? 1 : 0;
 }
 
+template <int Tag>
 __global__ __launch_bounds__(kThreads) void k_tile_hist(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
                                                         const int64_t *n_dev, int64_t n_max, int64_t tiles_max,
                                                         int shift, const int32_t *ctl, int pass,
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const uint64_t *__restri
     hist[(int64_t)threadIdx.x * tiles_max + blockIdx.x] = h[threadIdx.x];
 }
 
+template <int Tag>
 __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
                                                       uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
                                                       const int64_t *n_dev, int64_t n_max, int64_t tiles_max, int shift,
@@ -179,18 +181,23 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
     return JABBA_OK;
 }
 
-int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st) {
+int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag) {
+    const bool main_sort = !tag || !tag[0];
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
     JB_LAUNCH(k_plan, dim3(1), dim3(512), 0, st, b.ghist, n_dev, n_max, b.ctl);
     JB_LAUNCH_CHECK();
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
-        JB_LAUNCH(k_tile_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], n_dev,
+        JB_LAUNCH_NAMED(main_sort ? "k_tile_hist" : "k_tile_hist_groups",
+                        main_sort ? k_tile_hist<0> : k_tile_hist<1>, dim3((unsigned)tiles),
+                        dim3(kThreads), 0, st, b.keys[0], b.keys[1], n_dev,
                            n_max, tiles, shift, b.ctl, pass, b.hist);
         JB_LAUNCH_CHECK();
         int rc = scan_u32_to_u32(b.hist, b.hist, nullptr, 256 * tiles, b.scan_ws, st);
         if (rc) return rc;
-        JB_LAUNCH(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0],
+        JB_LAUNCH_NAMED(main_sort ? "k_scatter" : "k_scatter_groups",
+                        main_sort ? k_scatter<0> : k_scatter<1>, dim3((unsigned)tiles),
+                        dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0],
                            b.vals[1], n_dev, n_max, tiles, shift, b.ctl, pass, b.hist);
         JB_LAUNCH_CHECK();
         JB_LAUNCH(k_flip, dim3(1), dim3(64), 0, st, b.ctl, pass);

@@ -1,0 +1,129 @@
+"""Condense rocprofv3 output into the short text summaries kept under profiles/.
+
+    python -m paper_2401_00109_amd.rocprof_summary \\
+        --trace <dir with *_kernel_stats.csv> --fetch <FETCH_SIZE counter csv> \\
+        --write <WRITE_SIZE counter csv> --workload scale --command "<cmd>" --out profiles
+
+HBM traffic per dispatch comes from two counter runs (FETCH_SIZE, then
+WRITE_SIZE, in KiB per dispatch).  Each counter is scaled by what it reads
+for a plain copy kernel of known size that the benchmark launches in the
+same run (``--pmc-calibrate``: torch.neg over 1 GiB, reading and writing
+1 GiB), so the factor corrects the counter's granularity on this device.
+traffic.json records the source hash of the kernels; the benchmark ignores
+it once the kernel sources change.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CAL_BYTES = float(1 << 30)
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources; identifies the kernels a measurement belongs to."""
+    h = hashlib.sha256()
+    d = os.path.join(PKG, "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def timing_name(kernel: str) -> str:
+    """rocprof's demangled kernel name -> the library's timing name."""
+    m = re.search(r"::(k_[A-Za-z0-9_]+)(<[^()]*>)?\(", kernel)
+    if not m:
+        return kernel.split("(")[0][-60:]
+    base, targs = m.group(1), (m.group(2) or "")
+    if base == "k_compress":
+        return "k_compress<W>"
+    if base in ("k_scatter", "k_tile_hist"):
+        return base + ("_groups" if targs == "<1>" else "")
+    return base + targs
+
+
+def load_counter(path: str, counter: str):
+    per = collections.defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") == counter:
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def calibration(per: dict) -> float | None:
+    vals = [v for name, vs in per.items() if "neg_kernel" in name for v in vs]
+    if not vals:
+        return None
+    return CAL_BYTES / (sum(vals) / len(vals) * 1024.0)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", default="scale")
+    ap.add_argument("--command", default="")
+    ap.add_argument("--out", default="profiles")
+    args = ap.parse_args()
+
+    stats_csv = glob.glob(os.path.join(args.trace, "*kernel_stats.csv"))[0]
+    with open(stats_csv) as fh:
+        stats = list(csv.DictReader(fh))
+    fetch = load_counter(args.fetch, "FETCH_SIZE")
+    write = load_counter(args.write, "WRITE_SIZE")
+    ff, wf = calibration(fetch), calibration(write)
+
+    traffic = {}
+    for name in set(fetch) | set(write):
+        if "jabba" not in name:
+            continue
+        f = fetch.get(name, [])
+        w = write.get(name, [])
+        fb = (sum(f) / len(f) * 1024.0 * ff) if (f and ff) else None
+        wb = (sum(w) / len(w) * 1024.0 * wf) if (w and wf) else None
+        tn = timing_name(name)
+        traffic[tn] = {"rocprof_name": name[:name.find("(", name.find("::k_"))] if "::k_" in name else name[:80],
+                       "dispatches": len(f),
+                       "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                       "bytes_per_launch": (fb or 0.0) + (wb or 0.0) if (fb is not None and wb is not None) else None}
+
+    os.makedirs(args.out, exist_ok=True)
+    with open(os.path.join(args.out, "traffic.json"), "w") as fh:
+        json.dump({"source_hash": source_hash(), "workload": args.workload, "fetch_factor": ff, "write_factor": wf,
+                   "calibration": "torch.neg over 1 GiB of float64 (1 GiB read + 1 GiB written per launch)",
+                   "kernels": traffic}, fh, indent=1, sort_keys=True)
+
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# Kernel time and HBM traffic, workload `{args.workload}`", "",
+             f"Command: `{args.command}`", "",
+             f"Source hash of the kernels: `{source_hash()}`", "",
+             f"Counter scaling from the 1 GiB copy kernel: FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {wf:.4f}"
+             if ff and wf else "Counter scaling: calibration kernel missing", "",
+             "| kernel | calls | total ms | avg us | % | fetch MB/launch | write MB/launch |",
+             "|---|---|---|---|---|---|---|"]
+    for r in stats[:24]:
+        tn = timing_name(r["Name"])
+        t = traffic.get(tn, {})
+        fb, wb = t.get("fetch_bytes_per_launch"), t.get("write_bytes_per_launch")
+        lines.append(f"| {tn} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} | "
+                     f"{'' if fb is None else f'{fb / 1e6:.1f}'} | {'' if wb is None else f'{wb / 1e6:.1f}'} |")
+    path = os.path.join(args.out, f"kernels_{args.workload}.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
