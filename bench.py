@@ -120,11 +120,9 @@ def main() -> int:
                                    0.0)).to(dev)
 
     # resident serving dictionary: built once from the 16 x 1,000 random walks
+    from paper_2401_00109_amd.serve import build_resident_dictionary
     w1 = make_workload(1, seed=0)
-    s1 = J.Symbolizer(w1.n_series, w1.n_points, w1.D, w1.tol, w1.alpha, w1.scl, w1.B)
-    s1.run(torch.from_numpy(w1.values).to(dev), torch.from_numpy(w1.series_off).to(dev))
-    resident = s1.dictionary
-    torch.cuda.synchronize()
+    resident = build_resident_dictionary(dev)
     log(f"resident dictionary: k={resident.size()}")
 
     # size the digitize buffers from the actual piece count (one warm-up compress)

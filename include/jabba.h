@@ -81,7 +81,8 @@ typedef struct jabba_tuning {
                                  the workgroup's staging buffers would exceed 64 KB)   */
     int32_t blocks_per_cu;    /* compress: persistent workgroups per compute unit, 1..32 */
     int32_t stage1_waves;     /* digitize Stage I: wavefronts per workgroup (one block
-                                 of sorted pieces per wavefront), 1..16                 */
+                                 of sorted pieces per wavefront), 1..16 (halved until
+                                 the workgroup's LDS fits in 64 KB, i.e. at most 4)     */
     int32_t reserved[4];
 } jabba_tuning;
 

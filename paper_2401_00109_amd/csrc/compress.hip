@@ -116,10 +116,15 @@ __global__ void k_prepare(int32_t *status, int32_t *q_head) {
 }
 
 // Ring of staged points per group (positions p live in slot p & (R - 1)).
+// Small rings keep every group of a launch resident at once (the LDS of a
+// compute unit holds ~160 groups of 64 points); the next Q points are always
+// in flight in registers, so a refill only moves them into the ring.
 template <int W>
 struct RingShape {
-    static constexpr int R = W >= 4 ? 128 : (W == 2 ? 64 : 32);
+    static constexpr int R = W >= 8 ? 128 : (W >= 2 ? 64 : 32);
     static constexpr int Q = R / 2;  // refill granularity
+    static_assert(W <= R - Q, "a refill must not overwrite the window a round reads");
+    static_assert(Q % W == 0, "each lane stages Q / W points per refill");
 };
 
 template <int W>
@@ -155,6 +160,16 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     double ts = 0.0;
     int32_t c0 = 2;
     double S2c = 0.0, S1c = 0.0;  // sums over the terms of candidates below c0
+    double pre[Q / W];            // points [le, le + Q), loaded ahead of the refill that stages them
+
+    // requests [le, le + Q): lane j holds points le + r * W + j
+    auto prefetch = [&]() {
+#pragma unroll
+        for (int r = 0; r < Q / W; ++r) {
+            const int64_t p = le + r * W + j;
+            pre[r] = p <= e ? t[p] : 0.0;
+        }
+    };
 
     auto start_domain = [&](int32_t d) {
         dom = d;
@@ -169,10 +184,15 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
         c0 = 2;
         S2c = 0.0;
         S1c = 0.0;
+        prefetch();
     };
-    // point p (s <= p <= e) of the current domain: staged or, for pieces
-    // longer than the ring holds, straight from memory
-    auto at = [&](int64_t p) -> double { return p < le ? ring[p & (R - 1)] : t[p]; };
+    // The ring holds positions [le - R, le).  A round reads only the window
+    // [s + c0 - 1, s + c0 + W - 1], which the refill keeps staged, so the
+    // round's own reads never wait on global memory (and so never on the
+    // output stores still in flight).  Only the exact evaluation of an
+    // undecided candidate may reach below the ring, and reads memory there.
+    auto at = [&](int64_t p) -> double { return ring[p & (R - 1)]; };
+    auto at_far = [&](int64_t p) -> double { return p >= le - R ? ring[p & (R - 1)] : t[p]; };
 
     if (direct) {
         const int64_t d = direct_base + wave_g * (kWave / W) + lane / W;
@@ -214,12 +234,14 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
             // stage the points this round reads: [s + c0 - 1, s + c0 + W - 1]
             int64_t need_hi = s + c0 + W - 1;
             if (need_hi > e) need_hi = e;
-            while (le <= need_hi && le + Q - R <= s) {
-                for (int m = j; m < Q; m += W) {
-                    const int64_t p = le + m;
-                    if (p <= e) ring[p & (R - 1)] = t[p];
-                }
+            // refill Q points at a time from the registers loaded ahead,
+            // then request the next Q.  Overwritten slots hold
+            // [le - R, le - R + Q), below the window because W <= R - Q.
+            while (le <= need_hi) {
+#pragma unroll
+                for (int r = 0; r < Q / W; ++r) ring[(le + r * W + j) & (R - 1)] = pre[r];
                 le += Q;
+                prefetch();
             }
             c = c0 + j;
             const int64_t pk = s + c - 1;  // the term this candidate adds: k = c - 1
@@ -254,7 +276,7 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
                     for (int32_t k = 1; k < c; ++k) {
                         double v = b * (double)k;
                         v = ts + v;
-                        const double r = v - at(s + k);
+                        const double r = v - at_far(s + k);
                         acc = acc + r * r;
                     }
                     verdict = (acc <= thr) ? 1 : -1;

@@ -3,7 +3,7 @@
 //
 // Data flow (N pieces, all counts stay on the device):
 //   len/inc (canonical) --sum passes--> sigma_len, sigma_inc
-//   --k_key--> (key bits, index) --radix sort--> sorted order (perm)
+//   --k_key--> (key bits, index), piece records --radix sort--> sorted order (perm)
 //   --k_gather--> sorted arrays key/x/y/len/inc (contiguous for Stage I)
 //   --k_cuts--> blocks of B sorted pieces, cuts moved past equal keys
 //   --k_stage1 (one wavefront per block)--> local start per piece, start flags,
@@ -185,18 +185,33 @@ __global__ void k_sigma(DigState *ds, const double *total2, double scl, double a
     }
 }
 
+// One piece as a 16-byte record, so that reading it in sorted (random)
+// order touches one cache line instead of one per array.
+struct __align__(16) PieceRec {
+    double inc;
+    int32_t len;
+    int32_t pad;
+};
+
 __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict__ inc, const DigState *ds, double scl,
-                      uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                      uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, PieceRec *__restrict__ rec) {
     const int64_t n = ds->n;
     const double sl = ds->sigma_len, si = ds->sigma_inc;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const Scaled s = scale_piece(len[i], inc[i], scl, sl, si);
+        const int32_t l = len[i];
+        const double ic = inc[i];
+        const Scaled s = scale_piece(l, ic, scl, sl, si);
         keys[i] = (uint64_t)__double_as_longlong(piece_key(s));
         vals[i] = (uint32_t)i;
+        PieceRec r;
+        r.inc = ic;
+        r.len = l;
+        r.pad = 0;
+        rec[i] = r;
     }
 }
 
-__global__ void k_gather(const int32_t *__restrict__ len, const double *__restrict__ inc, DigState *ds,
+__global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds,
                          double scl, const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
                          const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
                          double *__restrict__ sk, double *__restrict__ sx, double *__restrict__ sy,
@@ -212,8 +227,9 @@ __global__ void k_gather(const int32_t *__restrict__ len, const double *__restri
     }
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t c = vs[p];
-        const int32_t l = len[c];
-        const double ic = inc[c];
+        const PieceRec r = rec[c];
+        const int32_t l = r.len;
+        const double ic = r.inc;
         const Scaled s = scale_piece(l, ic, scl, sl, si);
         sk[p] = __longlong_as_double((long long)ks[p]);
         sx[p] = s.x;
@@ -256,6 +272,7 @@ __global__ void k_cuts(const double *__restrict__ sk, const DigState *ds, int64_
 // current ones are tested.
 
 constexpr int kActCap = 256;  // active starts cached in LDS per wavefront
+constexpr int kStage = 4;     // batches of 64 points staged in LDS at a time
 
 struct ActLds {
     double k[kActCap];
@@ -264,8 +281,12 @@ struct ActLds {
     int32_t p[kActCap];
 };
 
-// Active starts: an append-only list of positions in global memory (glist),
-// the newest kActCap of them mirrored in LDS with their coordinates.
+// Active starts: an append-only list of positions (glist in global memory),
+// the newest kActCap of them mirrored in LDS with their coordinates.  New
+// entries go to LDS only; flush() copies them to glist once per staged
+// chunk, before any of them can leave the mirror (a chunk pushes at most
+// kStage * 64 = kActCap entries).  Reads of entries no longer mirrored take
+// their own loop, so the common path (LDS only) never waits on memory.
 struct Active {
     ActLds *c;
     int32_t *glist;
@@ -278,39 +299,24 @@ struct Active {
             c->x[sl] = xp;
             c->y[sl] = yp;
             c->p[sl] = pos;
-            __hip_atomic_store(&glist[tail], pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         ++tail;
     }
-    __device__ bool cached(int i) const { return tail - i <= kActCap; }
-    __device__ void get(int i, const double *key, const double *x, const double *y, double &kp, double &xp,
-                        double &yp, int32_t &pp) const {
-        if (cached(i)) {
-            const int sl = i % kActCap;
-            kp = c->k[sl];
-            xp = c->x[sl];
-            yp = c->y[sl];
-            pp = c->p[sl];
-        } else {
-            pp = __hip_atomic_load(&glist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            kp = key[pp];
-            xp = x[pp];
-            yp = y[pp];
-        }
+    // entries [from, tail) to glist
+    __device__ void flush(int from) {
+        for (int t = from + lane_id(); t < tail; t += kWave)
+            __hip_atomic_store(&glist[t], c->p[t % kActCap], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __device__ int first_cached() const { return tail - kActCap > head ? tail - kActCap : head; }
     // drop starts that no point with key >= k0 can reach
     __device__ void expire(double k0, double alpha, const double *key) {
-        while (head < tail) {
-            double kh;
-            if (cached(head))
-                kh = c->k[head % kActCap];
-            else
-                kh = key[__hip_atomic_load(&glist[head], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)];
-            if (!(k0 - kh <= alpha))
-                ++head;
-            else
-                break;
+        const int fc = first_cached();
+        while (head < fc) {
+            const double kh = key[__hip_atomic_load(&glist[head], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)];
+            if (!(k0 - kh <= alpha)) ++head;
+            else return;
         }
+        while (head < tail && !(k0 - c->k[head % kActCap] <= alpha)) ++head;
     }
 };
 
@@ -326,59 +332,104 @@ __device__ __forceinline__ bool covers(double kq, double xq, double yq, double k
 
 // Runs the greedy over positions [from, to) with the active list A as the
 // state before `from`.  Owners are written to lab/flag when `write`.
+// Points are staged kStage batches at a time (all loads of a chunk in flight
+// together); within a batch each lane first tests its point against the
+// active starts, oldest first, and the points no active start covers are
+// then resolved among themselves in lane order (one step per new start).
 __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__restrict__ key,
                            const double *__restrict__ x, const double *__restrict__ y, double alpha, double a2,
                            bool write, int32_t *__restrict__ lab, uint32_t *__restrict__ flag,
-                           int32_t *__restrict__ start_end = nullptr, int32_t range_end = 0) {
+                           int32_t *__restrict__ start_tag = nullptr, int32_t tag = 0) {
     const int lane = lane_id();
-    double kn = 0.0, xn = 0.0, yn = 0.0;
-    if (from + lane < to) {
-        kn = key[from + lane];
-        xn = x[from + lane];
-        yn = y[from + lane];
-    }
-    for (int64_t b0 = from; b0 < to; b0 += kWave) {
-        const int64_t q = b0 + lane;
-        const bool inr = q < to;
-        const double kq = kn, xq = xn, yq = yn;
-        if (b0 + kWave + lane < to) {  // next batch, loaded while this one is tested
-            kn = key[b0 + kWave + lane];
-            xn = x[b0 + kWave + lane];
-            yn = y[b0 + kWave + lane];
+    ActLds *L = A.c;
+    for (int64_t c0 = from; c0 < to; c0 += kStage * kWave) {
+        // the chunk's points in registers; batch r always reads slot 0 and
+        // the slots rotate after each batch (static register indices)
+        double kv[kStage], xv[kStage], yv[kStage];
+        int32_t ov[kStage];
+#pragma unroll
+        for (int r = 0; r < kStage; ++r) {
+            const int64_t p = c0 + r * kWave + lane;
+            kv[r] = p < to ? key[p] : 0.0;
+            xv[r] = p < to ? x[p] : 0.0;
+            yv[r] = p < to ? y[p] : 0.0;
+            ov[r] = -1;
         }
-        A.expire(__shfl(kq, 0), alpha, key);
-        if (A.head < A.tail && !A.cached(A.head)) __threadfence();
-        int32_t owner = -1;
-        bool open = inr;
-        for (int i = A.head; i < A.tail; ++i) {
-            if (ballot(open) == 0ull) break;
-            double kp, xp, yp;
-            int32_t pp;
-            A.get(i, key, x, y, kp, xp, yp, pp);
-            if (open && covers(kq, xq, yq, kp, xp, yp, alpha, a2)) {
-                owner = pp;
-                open = false;
+        const int64_t c1 = to < c0 + kStage * kWave ? to : c0 + kStage * kWave;
+        const int tail0 = A.tail;
+        for (int r = 0; r < kStage; ++r) {
+            const int64_t b0 = c0 + (int64_t)r * kWave;
+            const int64_t q = b0 + lane;
+            const bool inr = q < to;
+            const double kq = kv[0], xq = xv[0], yq = yv[0];
+            int32_t owner = -1;
+            if (b0 < c1) {
+                // list entries that left the LDS mirror are read back from memory
+                if (A.head < A.first_cached()) __threadfence();
+                A.expire(__shfl(kq, 0), alpha, key);
+                bool open = inr;
+                int i = A.head;
+                const int fc = A.first_cached();
+                if (i < fc) {
+                    for (; i < fc; ++i) {
+                        if (ballot(open) == 0ull) break;
+                        const int32_t pp = __hip_atomic_load(&A.glist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (open && covers(kq, xq, yq, key[pp], x[pp], y[pp], alpha, a2)) {
+                            owner = pp;
+                            open = false;
+                        }
+                    }
+                }
+                if (i >= fc) {
+                    for (; i < A.tail; ++i) {
+                        if (ballot(open) == 0ull) break;
+                        const int e = i % kActCap;
+                        if (open && covers(kq, xq, yq, L->k[e], L->x[e], L->y[e], alpha, a2)) {
+                            owner = L->p[e];
+                            open = false;
+                        }
+                    }
+                }
+                // the points no active start covers, resolved in lane order:
+                // the first becomes a start and covers later lanes, and so on
+                uint64_t pend = ballot(open);
+                while (pend) {
+                    const int l = ffs64(pend);
+                    const double kl = __shfl(kq, l), xl = __shfl(xq, l), yl = __shfl(yq, l);
+                    const int32_t pl = (int32_t)(b0 + l);
+                    if (lane == l) {
+                        owner = pl;
+                        open = false;
+                    } else if (open && lane > l && covers(kq, xq, yq, kl, xl, yl, alpha, a2)) {
+                        owner = pl;
+                        open = false;
+                    }
+                    A.push(pl, kl, xl, yl);
+                    pend = ballot(open);
+                }
             }
-        }
-        uint64_t pend = ballot(open);
-        while (pend) {
-            const int l = ffs64(pend);
-            const double kl = __shfl(kq, l), xl = __shfl(xq, l), yl = __shfl(yq, l);
-            const int32_t pl = (int32_t)(b0 + l);
-            if (lane == l) {
-                owner = pl;
-                open = false;
-            } else if (open && lane > l && covers(kq, xq, yq, kl, xl, yl, alpha, a2)) {
-                owner = pl;
-                open = false;
+#pragma unroll
+            for (int i = 0; i + 1 < kStage; ++i) {
+                kv[i] = kv[i + 1];
+                xv[i] = xv[i + 1];
+                yv[i] = yv[i + 1];
+                ov[i] = ov[i + 1];
             }
-            A.push(pl, kl, xl, yl);
-            pend = ballot(open);
+            ov[kStage - 1] = owner;
         }
-        if (write && inr) {
-            lab[q] = owner;
-            flag[q] = owner == (int32_t)q ? 1u : 0u;
-            if (start_end && owner == (int32_t)q) start_end[q] = range_end;
+        // the chunk's owners and new list entries leave together
+        A.flush(tail0);
+        if (write) {
+#pragma unroll
+            for (int r = 0; r < kStage; ++r) {
+                const int64_t q = c0 + r * kWave + lane;
+                if (q < c1) {
+                    const int32_t owner = ov[r];
+                    lab[q] = owner;
+                    flag[q] = owner == (int32_t)q ? 1u : 0u;
+                    if (start_tag && owner == (int32_t)q) start_tag[q] = tag;
+                }
+            }
         }
     }
 }
@@ -388,7 +439,7 @@ __global__ __launch_bounds__(1024) void k_stage1(const int64_t *__restrict__ cut
                                                  const double *__restrict__ sk, const double *__restrict__ sx,
                                                  const double *__restrict__ sy, double alpha, double a2,
                                                  int32_t *__restrict__ glist, int32_t *__restrict__ lab,
-                                                 uint32_t *__restrict__ flag, int32_t *__restrict__ start_end) {
+                                                 uint32_t *__restrict__ flag, int32_t *__restrict__ start_blk) {
     extern __shared__ ActLds act_lds[];
     const int wave = threadIdx.x / kWave;
     const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
@@ -396,7 +447,7 @@ __global__ __launch_bounds__(1024) void k_stage1(const int64_t *__restrict__ cut
     const int64_t lo = cuts[blk], hi = cuts[blk + 1];
     if (lo >= hi) return;
     Active A{&act_lds[wave], glist + lo, 0, 0};
-    pull_range(lo, hi, A, sk, sx, sy, alpha, a2, true, lab, flag, start_end, (int32_t)hi);
+    pull_range(lo, hi, A, sk, sx, sy, alpha, a2, true, lab, flag, start_blk, (int32_t)blk);
 }
 
 // Stage II runs on independent groups of starting points.  Two starting
@@ -492,14 +543,127 @@ __global__ __launch_bounds__(256) void k_col_greedy(const int64_t *__restrict__ 
     }
 }
 
-// Per-start sums over the start's members (lab == start), in position order:
-// one pairwise wavefront sum per 64 positions, chunks added in order.  The
-// members of a start lie in its alpha-window of keys after it.
+// Per-start sums over the start's members (lab == start).
+//
+// Stage I groups never leave their block, so a block's sums need one pass
+// over its points: k_block_sums takes one wavefront per block and keeps the
+// block's accumulators in LDS (blocks with at most kBlkCap starts).  Each
+// batch of 64 points is ordered by (local start, position) with a bitonic
+// network across the lanes; a segmented scan then sums each start's members
+// of the batch, and the segment's last lane adds that partial to the start's
+// accumulator.  Batches are added in position order, so the floating-point
+// order is fixed by the data alone.  Blocks with more starts take
+// k_group_sums<true>, one wavefront per start scanning the start's
+// alpha-window of keys in chunks of 64 positions added in order.
+constexpr int kBlkCap = 512;  // starts per block summed in LDS
+constexpr int kSumStage = 8;  // batches of 64 points loaded together
+
+struct SumLds {
+    unsigned long long len[kBlkCap];
+    double inc[kBlkCap];
+    uint32_t cnt[kBlkCap];
+};
+
+__device__ __forceinline__ int64_t block_starts(const int64_t *__restrict__ cuts, const uint32_t *__restrict__ sidx,
+                                                int64_t blk) {
+    return (int64_t)sidx[cuts[blk + 1]] - (int64_t)sidx[cuts[blk]];
+}
+
+__global__ __launch_bounds__(256) void k_block_sums(const int64_t *__restrict__ cuts, int64_t nblk_max,
+                                                    const uint32_t *__restrict__ sidx, const int32_t *__restrict__ lab,
+                                                    const int32_t *__restrict__ slen, const double *__restrict__ sinc,
+                                                    int64_t *__restrict__ ocnt, int64_t *__restrict__ olen,
+                                                    double *__restrict__ oinc) {
+    __shared__ SumLds sums_all[256 / kWave];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int64_t blk = (int64_t)blockIdx.x * (256 / kWave) + wave;
+    if (blk >= nblk_max) return;
+    const int64_t lo = cuts[blk], hi = cuts[blk + 1];
+    if (lo >= hi) return;
+    const uint32_t g0 = sidx[lo];
+    const int64_t ns = (int64_t)sidx[hi] - (int64_t)g0;
+    if (ns < 1 || ns > kBlkCap) return;
+    SumLds &S = sums_all[wave];
+    for (int j = lane; j < ns; j += kWave) {
+        S.len[j] = 0ull;
+        S.inc[j] = 0.0;
+        S.cnt[j] = 0u;
+    }
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    for (int64_t c0 = lo; c0 < hi; c0 += kSumStage * kWave) {
+        int32_t own[kSumStage], lv[kSumStage];
+        double iv[kSumStage];
+        uint32_t key[kSumStage];
+#pragma unroll
+        for (int r = 0; r < kSumStage; ++r) {
+            const int64_t q = c0 + r * kWave + lane;
+            own[r] = q < hi ? lab[q] : -1;
+            lv[r] = q < hi ? slen[q] : 0;
+            iv[r] = q < hi ? sinc[q] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kSumStage; ++r) {
+            key[r] = kNone;
+            if (own[r] >= 0) {
+                const int64_t li = (int64_t)sidx[own[r]] - (int64_t)g0;
+                if (li >= 0 && li < ns) key[r] = ((uint32_t)li << 6) | (uint32_t)lane;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kSumStage; ++r) {
+            if (c0 + r * kWave >= hi) break;
+            // ascending bitonic sort of the 64 keys across the lanes
+            uint32_t k = key[r];
+#pragma unroll
+            for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    const uint32_t o = __shfl_xor(k, stride);
+                    const bool up = (lane & size) == 0 || size == kWave;
+                    const bool low = (lane & stride) == 0;
+                    k = (low == up) ? (k < o ? k : o) : (k < o ? o : k);
+                }
+            }
+            const int src = (int)(k & 63u);
+            const uint32_t seg = k >> 6;
+            double v = __shfl(iv[r], src);
+            long long l = (long long)__shfl(lv[r], src);
+            uint32_t c = k != kNone ? 1u : 0u;
+            // segmented inclusive scan over runs of equal seg
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const double yv = __shfl_up(v, d);
+                const long long yl = __shfl_up(l, d);
+                const uint32_t yc = __shfl_up(c, d);
+                const uint32_t ys = __shfl_up(seg, d);
+                if (lane >= d && ys == seg) {
+                    v = v + yv;
+                    l += yl;
+                    c += yc;
+                }
+            }
+            const uint32_t nx = __shfl_down(seg, 1);
+            if (k != kNone && (lane == kWave - 1 || nx != seg)) {
+                S.inc[seg] = S.inc[seg] + v;
+                S.len[seg] += (unsigned long long)l;
+                S.cnt[seg] += c;
+            }
+        }
+    }
+    for (int j = lane; j < ns; j += kWave) {
+        ocnt[g0 + j] = (int64_t)S.cnt[j];
+        olen[g0 + j] = (int64_t)S.len[j];
+        oinc[g0 + j] = S.inc[j];
+    }
+}
+
 template <bool Points>
 __global__ __launch_bounds__(256) void k_group_sums(const int64_t *__restrict__ n_starts_p, int64_t n_pos_max,
                                                     const int64_t *__restrict__ n_pos_p,
                                                     const int32_t *__restrict__ start_pos,
-                                                    const int32_t *__restrict__ start_end,
+                                                    const int32_t *__restrict__ start_blk,
+                                                    const int64_t *__restrict__ cuts, const uint32_t *__restrict__ sidx,
                                                     const uint32_t *__restrict__ flag, const double *__restrict__ key,
                                                     const int32_t *__restrict__ lab, const int32_t *__restrict__ wlen32,
                                                     const int64_t *__restrict__ wcnt, const int64_t *__restrict__ wlen,
@@ -515,7 +679,9 @@ __global__ __launch_bounds__(256) void k_group_sums(const int64_t *__restrict__ 
         int64_t p, pend = n_pos;
         if (Points) {
             p = start_pos[g];
-            pend = start_end[p];  // members never leave the start's block
+            const int64_t blk = start_blk[p];
+            if (block_starts(cuts, sidx, blk) <= kBlkCap) continue;  // summed by k_block_sums
+            pend = cuts[blk + 1];  // members never leave the start's block
         } else {
             if (!flag[g]) continue;
             p = g;
@@ -609,6 +775,7 @@ struct DigWs {
     double *sk, *sx, *sy, *sinc;
     int32_t *slen;
     uint32_t *perm;
+    PieceRec *rec;
     int64_t *cuts;
     int32_t *lab;
     uint32_t *flag;
@@ -631,7 +798,7 @@ struct DigWs {
     double *ck, *cx, *cy;
     int32_t *own;
     uint32_t *oflag;
-    int32_t *send;
+    int32_t *sblk;
     void *scan_ws;
     size_t bytes;
 };
@@ -655,6 +822,7 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     w.sinc = c.take<double>(N);
     w.slen = c.take<int32_t>(N);
     w.perm = c.take<uint32_t>(N);
+    w.rec = c.take<PieceRec>(N);
     w.cuts = c.take<int64_t>(nblk + 2);
     w.lab = c.take<int32_t>(N);
     w.flag = c.take<uint32_t>(N);
@@ -684,7 +852,7 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     w.cy = c.take<double>(N);
     w.own = c.take<int32_t>(N);
     w.oflag = c.take<uint32_t>(N);
-    w.send = c.take<int32_t>(N);
+    w.sblk = c.take<int32_t>(N);
     w.scan_ws = c.take<char>(scan_workspace(N + 1));
     w.bytes = c.bytes();
     return w;
@@ -750,6 +918,7 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     int s1w = 4;
     if (tuning && tuning->stage1_waves) s1w = tuning->stage1_waves;
     if (s1w < 1 || s1w > 16) return JABBA_EINVAL;
+    while (s1w > 1 && (size_t)s1w * sizeof(ActLds) > 65536) s1w >>= 1;  // keep the workgroup's LDS <= 64 KB
     const double a2 = alpha * alpha;
 
     JB_LAUNCH(k_dig_prepare, dim3(1), dim3(64), 0, st, w.ds, n_pieces, max_pieces);
@@ -775,14 +944,14 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     // key and global sorting index
     rc = radix_sort_init(w.sb, st);
     if (rc) return rc;
-    JB_LAUNCH(k_key, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH(k_key, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0], w.sb.vals[0], w.rec);
     JB_LAUNCH_CHECK();
     const int64_t *n_live = &w.ds->n;
     rc = radix_global_hist(w.sb, n_live, N, st);
     if (rc) return rc;
     rc = radix_sort_pairs(w.sb, n_live, N, st);
     if (rc) return rc;
-    JB_LAUNCH(k_gather, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0],
+    JB_LAUNCH(k_gather, dim3(grid_for(N)), dim3(256), 0, st, w.rec, w.ds, scl, w.sb.keys[0],
                        w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
     JB_LAUNCH_CHECK();
 
@@ -791,17 +960,20 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     JB_LAUNCH_CHECK();
     const size_t lds = (size_t)s1w * sizeof(ActLds);
     JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk, w.sk,
-              w.sx, w.sy, alpha, a2, w.glist, w.lab, w.flag, w.send);
+              w.sx, w.sy, alpha, a2, w.glist, w.lab, w.flag, w.sblk);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.flag, w.sidx, n_live, N, w.scan_ws, st);
     if (rc) return rc;
     JB_LAUNCH(k_compact_starts, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.flag, w.sidx, w.sk, w.sx, w.sy, w.gk,
               w.gx, w.gy, w.spos, w.g_count);
     JB_LAUNCH_CHECK();
-    // partial sums of every local group, in position order
+    // sums of every local group: per block in LDS, per start for crowded blocks
+    JB_LAUNCH(k_block_sums, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, st, w.cuts, nblk, w.sidx, w.lab,
+              w.slen, w.sinc, w.gcnt, w.glen, w.ginc);
+    JB_LAUNCH_CHECK();
     JB_LAUNCH((k_group_sums<true>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, n_live, w.spos,
-              w.send, w.flag, w.sk, w.lab, w.slen, (const int64_t *)nullptr, (const int64_t *)nullptr, w.sinc, alpha, w.gcnt,
-              w.glen, w.ginc);
+              w.sblk, w.cuts, w.sidx, w.flag, w.sk, w.lab, w.slen, (const int64_t *)nullptr, (const int64_t *)nullptr,
+              w.sinc, alpha, w.gcnt, w.glen, w.ginc);
     JB_LAUNCH_CHECK();
 
     // Stage II over the starting points: independent groups (length column,
@@ -828,7 +1000,8 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
     JB_LAUNCH((k_group_sums<false>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, w.g_count,
-              (const int32_t *)nullptr, (const int32_t *)nullptr, w.gflag, w.gk, w.glab, (const int32_t *)nullptr, w.gcnt, w.glen, w.ginc,
+              (const int32_t *)nullptr, (const int32_t *)nullptr, (const int64_t *)nullptr, (const uint32_t *)nullptr,
+              w.gflag, w.gk, w.glab, (const int32_t *)nullptr, w.gcnt, w.glen, w.ginc,
               alpha, w.ocnt, w.olen, w.oinc);
     JB_LAUNCH_CHECK();
     JB_LAUNCH(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen, w.oinc, w.ds,

@@ -1,7 +1,7 @@
 // Inverse symbolization (Sec. 3.3): inverse digitization (symbol -> center),
 // quantization of the lengths (Eq. repolygon) and inverse compression.
 //
-// One wavefront per series walks its pieces 64 at a time.
+// Pieces are taken 64 at a time (one chunk per wavefront step).
 //  * Quantization: the carry rule keeps sum(len^_1..j) = round(sum(len~_1..j)),
 //    halves away from zero.  Every center length >= 1 is an integer multiple
 //    of 2^-52, so the running sums are exact unsigned 128-bit integers at
@@ -73,22 +73,47 @@ struct Src {
     int64_t k;
     const int32_t *len;
     const double *inc;
-    __device__ void get(int64_t j, u128 &lt, double &it, bool &ok) const {
+    // first load of piece j: its symbol (dictionary form) or nothing
+    __device__ int32_t tag(int64_t j) const { return center_len ? sym[j] : 0; }
+    // second load: the piece's raw length and increment
+    struct Raw {
+        double l;
+        double it;
+        int32_t li;
+        bool bad;
+    };
+    __device__ Raw load(int64_t j, int32_t c) const {
+        Raw r{0.0, 0.0, 0, false};
         if (center_len) {
-            const int32_t c = sym[j];
             if (c < 0 || c >= k) {
+                r.bad = true;
+            } else {
+                r.l = center_len[c];
+                r.it = center_inc[c];
+            }
+        } else {
+            r.li = len[j];
+            r.it = inc[j];
+        }
+        return r;
+    }
+    // the length as a fixed-point integer (an invalid symbol reads as length 1, increment 0)
+    __device__ void convert(const Raw &r, u128 &lt, double &it, bool &ok) const {
+        if (center_len) {
+            if (r.bad) {
                 ok = false;
                 lt = (u128)1 << 52;
                 it = 0.0;
                 return;
             }
-            lt = to_fixed(center_len[c], ok);
-            it = center_inc[c];
+            lt = to_fixed(r.l, ok);
+            it = r.it;
         } else {
-            lt = (u128)(uint32_t)len[j] << 52;
-            it = inc[j];
+            lt = (u128)(uint32_t)r.li << 52;
+            it = r.it;
         }
     }
+    __device__ void get(int64_t j, u128 &lt, double &it, bool &ok) const { convert(load(j, tag(j)), lt, it, ok); }
 };
 
 __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__restrict__ piece_off,
@@ -117,56 +142,119 @@ __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__r
     }
 }
 
-__global__ __launch_bounds__(256) void k_recon(Src src, const int64_t *__restrict__ piece_off,
-                                               const int64_t *__restrict__ out_off, int64_t n_series,
-                                               const double *__restrict__ t0, double *__restrict__ out,
-                                               int64_t *__restrict__ lhat) {
+// One workgroup per series.  Wavefront 0 produces chunks of 64 pieces (the
+// fixed-point scan of the lengths and the sequential values) into LDS while
+// the next chunk's loads are in flight; wavefront 1 fills the points of the
+// previous chunk, one point per thread (coalesced stores).  The two LDS
+// buffers alternate, one barrier per chunk.
+struct ReconChunk {
+    int64_t beg[kWave];  // S_{j-1}: offset of the piece's first point (its predecessor's end)
+    int64_t end[kWave];  // S_j
+    double vme[kWave];   // V_j
+    double slope[kWave];
+    double vin;          // V before the chunk's first piece
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+constexpr int kReconThreads = 128;
+constexpr int kFillThreads = kReconThreads - kWave;
+
+__global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t *__restrict__ piece_off,
+                                                         const int64_t *__restrict__ out_off, int64_t n_series,
+                                                         const double *__restrict__ t0, double *__restrict__ out,
+                                                         int64_t *__restrict__ lhat) {
+    __shared__ ReconChunk buf[2];
     const int lane = lane_id();
-    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
+    const bool producer = threadIdx.x < kWave;
+    for (int64_t s = blockIdx.x; s < n_series; s += gridDim.x) {
         const int64_t a = piece_off[s], b = piece_off[s + 1];
         const int64_t o = out_off[s];
-        if (out_off[s + 1] > o && lane == 0) out[o] = t0[s];
+        const int64_t nch = b > a ? (b - a + kWave - 1) / kWave : 0;
         u128 carryC = 0;
         int64_t carryS = 0;
-        double V = t0[s];
-        for (int64_t j0 = a; j0 < b; j0 += kWave) {
-            const int64_t j = j0 + lane;
-            const bool inr = j < b;
-            u128 lt = 0;
-            double it = 0.0;
-            bool ok = true;
-            if (inr) src.get(j, lt, it, ok);
-            // inclusive scan of the fixed-point center lengths
-            u128 C = lt;
+        double V = 0.0;
+        Src::Raw raw_n{0.0, 0.0, 0, false};
+        int32_t tag_n = 0;
+        if (producer) {
+            V = t0[s];
+            if (lane == 0 && out_off[s + 1] > o) out[o] = V;
+            if (nch > 0) {
+                const int64_t j = a + lane;
+                if (j < b) raw_n = src.load(j, src.tag(j));
+                if (j + kWave < b) tag_n = src.tag(j + kWave);
+            }
+        }
+        for (int64_t t = 0; t <= nch; ++t) {
+            if (producer && t < nch) {
+                const int64_t j0 = a + t * kWave;
+                const int64_t j = j0 + lane;
+                u128 lt = 0;
+                double it = 0.0;
+                if (j < b) {
+                    bool ok = true;
+                    src.convert(raw_n, lt, it, ok);
+                }
+                // the next chunk's loads, consumed one chunk later
+                raw_n = Src::Raw{0.0, 0.0, 0, false};
+                if (j + kWave < b) raw_n = src.load(j + kWave, tag_n);
+                tag_n = (j + 2 * kWave < b) ? src.tag(j + 2 * kWave) : 0;
+                // inclusive scan of the fixed-point center lengths
+                u128 C = lt;
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const u128 y = shfl_up_u128(C, d);
-                if (lane >= d) C += y;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const u128 y = shfl_up_u128(C, d);
+                    if (lane >= d) C += y;
+                }
+                C += carryC;
+                const int64_t S = fixed_round(C);
+                int64_t Sp = __shfl_up(S, 1);
+                if (lane == 0) Sp = carryS;
+                const int64_t lh = S - Sp;
+                // sequential running value: V is uniform across the lanes,
+                // each step adds the next piece's increment (a scalar read
+                // off the add chain) and every lane stores the same V_j
+                const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
+                ReconChunk &B = buf[t & 1];
+                if (lane == 0) B.vin = V;
+                for (int l = 0; l < cnt; ++l) {
+                    V = V + readlane_f64(it, l);
+                    B.vme[l] = V;
+                }
+                B.beg[lane] = Sp;
+                B.end[lane] = S;
+                B.slope[lane] = it / (double)lh;
+                carryC = shfl_u128(C, cnt - 1);
+                carryS = __shfl(S, cnt - 1);
             }
-            C += carryC;
-            const int64_t S = fixed_round(C);
-            int64_t Sp = __shfl_up(S, 1);
-            if (lane == 0) Sp = carryS;
-            const int64_t lh = S - Sp;
-            // sequential running value, lane by lane
-            const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
-            double Vprev = 0.0, Vme = 0.0;
-            for (int l = 0; l < cnt; ++l) {
-                const double il = __shfl(it, l);
-                if (lane == l) Vprev = V;
-                V = V + il;
-                if (lane == l) Vme = V;
+            if (!producer && t > 0) {
+                const int64_t tc = t - 1;
+                const int64_t j0 = a + tc * kWave;
+                const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
+                const ReconChunk &B = buf[tc & 1];
+                const int64_t lo = B.beg[0], hi = B.end[cnt - 1];
+                const int f = threadIdx.x - kWave;
+                for (int64_t r = lo + 1 + f; r <= hi; r += kFillThreads) {
+                    // first piece whose end is at or after point r
+                    int L = 0, H = cnt - 1;
+                    while (L < H) {
+                        const int M = (L + H) >> 1;
+                        if (B.end[M] >= r)
+                            H = M;
+                        else
+                            L = M + 1;
+                    }
+                    const double vprev = L > 0 ? B.vme[L - 1] : B.vin;
+                    out[o + r] = (r == B.end[L]) ? B.vme[L] : vprev + B.slope[L] * (double)(r - B.beg[L]);
+                }
+                if (lhat)
+                    for (int l = f; l < cnt; l += kFillThreads) lhat[j0 + l] = B.end[l] - B.beg[l];
             }
-            if (inr) {
-                if (lhat) lhat[j] = lh;
-                const double slope = it / (double)lh;
-                const int64_t base = o + Sp;
-                for (int64_t q = 1; q < lh; ++q) out[base + q] = Vprev + slope * (double)q;
-                out[o + S] = Vme;
-            }
-            carryC = shfl_u128(C, cnt - 1);
-            carryS = __shfl(S, cnt - 1);
+            __syncthreads();
         }
     }
 }
@@ -204,6 +292,15 @@ __global__ void k_recon_prep(int32_t *status) {
 
 unsigned waves_grid(int64_t n_series) {
     int64_t blocks = (n_series * kWave + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    return (unsigned)blocks;
+}
+
+// one workgroup per series, at most 16 resident per compute unit
+unsigned series_grid(int64_t n_series) {
+    int64_t blocks = n_series;
     const int64_t cap = (int64_t)device_cu_count() * 16;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
@@ -271,8 +368,8 @@ extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_of
     if (!t0 || !out || !series_off) return JABBA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
-    JB_LAUNCH(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
-                       out, lhat);
+    JB_LAUNCH(k_recon, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off, out_off, n_series,
+              t0, out, lhat);
     JB_LAUNCH_CHECK();
     if (values) {
         if (!sse || !cnt) return JABBA_EINVAL;
@@ -292,8 +389,8 @@ extern "C" int jabba_reconstruct_pieces(const int32_t *len, const double *inc, c
     int rc = sizes(src, piece_off, series_off, n_series, out_off, workspace, workspace_bytes, st);
     if (rc || n_series == 0) return rc;
     if (!t0 || !out) return JABBA_EINVAL;
-    JB_LAUNCH(k_recon, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, out_off, n_series, t0,
-                       out, (int64_t *)nullptr);
+    JB_LAUNCH(k_recon, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off, out_off, n_series,
+              t0, out, (int64_t *)nullptr);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }

@@ -9,7 +9,7 @@
 // stable scatter.  Inside a tile the elements are ranked in index order:
 // wavefront peers with the same digit are found with eight ballots, waves
 // are ordered through LDS counters, and rounds of 256 elements follow each
-// other.  A digit that is the same for every key is skipped; the decision is
+// other; the ranked tile is staged in LDS and leaves in digit order.  A digit that is the same for every key is skipped; the decision is
 // taken on the device from the global digit histograms, and the buffer that
 // holds the current order is tracked in device memory (ctl[0]), so no host
 // read-back is needed and the sort can be captured in a HIP graph.
@@ -84,6 +84,28 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const uint64_t *__restri
     hist[(int64_t)threadIdx.x * tiles_max + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan of one value per thread over the 256 threads of the block.
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_wave) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) s_wave[w] = x;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < w; ++q) add += s_wave[q];
+    return x - v + add;
+}
+
+// Stable scatter of one tile.  The tile is first ranked into LDS in digit
+// order (the rank of an element is its position among the tile's elements
+// with the same digit, in index order), then written out in that order, so
+// each digit's run of the tile lands in one contiguous stretch of the
+// destination and the stores of consecutive threads are coalesced.
 template <int Tag>
 __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
                                                       uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
@@ -91,9 +113,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0,
                                                       const int32_t *ctl, int pass,
                                                       const uint32_t *__restrict__ offs) {
     if (ctl[1 + pass]) return;
-    __shared__ uint32_t s_run[256];
+    __shared__ uint64_t s_key[kTileN];
+    __shared__ uint32_t s_val[kTileN];
+    __shared__ uint32_t s_run[256];  // next free local slot per digit
+    __shared__ uint32_t s_lo[256];   // local start per digit
+    __shared__ uint32_t s_go[256];   // destination start per digit
     __shared__ uint32_t s_cnt[kThreads / kWave][256];
     __shared__ uint32_t s_pre[kThreads / kWave][256];
+    __shared__ uint32_t s_wave[kThreads / kWave];
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const bool src1 = ctl[0] != 0;
@@ -104,15 +131,32 @@ __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0,
     const int64_t n = live(n_dev, n_max);
     const int64_t base = (int64_t)blockIdx.x * kTileN;
     if (base >= n) return;
-    s_run[tid] = offs[(int64_t)tid * tiles_max + blockIdx.x];
+    const int m = (int)(n - base < kTileN ? n - base : kTileN);
+
+    // all of this thread's elements in flight at once
+    uint64_t kr[kRounds];
+    uint32_t vr[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int li = r * kThreads + tid;
+        kr[r] = li < m ? ks[base + li] : 0ull;
+        vr[r] = li < m ? vs[base + li] : 0u;
+    }
+    // this tile's count of digit `tid`: difference of consecutive scanned
+    // offsets (digit-major layout; the entry after the last is the total)
+    const uint32_t g0 = offs[(int64_t)tid * tiles_max + blockIdx.x];
+    const uint32_t g1 = offs[(int64_t)tid * tiles_max + blockIdx.x + 1];
+    const uint32_t lo = block_excl_scan_256(g1 - g0, s_wave);
+    s_lo[tid] = lo;
+    s_run[tid] = lo;
+    s_go[tid] = g0;
     for (int i = 0; i < kThreads / kWave; ++i) s_cnt[i][tid] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
+#pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        const int64_t i = base + r * kThreads + tid;
-        const bool ok = i < n;
-        uint64_t key = ok ? ks[i] : 0ull;
-        uint32_t val = ok ? vs[i] : 0u;
+        const bool ok = r * kThreads + tid < m;
+        const uint64_t key = kr[r];
         const uint32_t dg = (uint32_t)(key >> shift) & 255u;
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -136,9 +180,21 @@ __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0,
         }
         __syncthreads();
         if (ok) {
-            const uint32_t pos = s_pre[w][dg] + rank;
+            const uint32_t lp = s_pre[w][dg] + rank;
+            s_key[lp] = key;
+            s_val[lp] = vr[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int j = r * kThreads + tid;
+        if (j < m) {
+            const uint64_t key = s_key[j];
+            const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+            const uint32_t pos = s_go[dg] + ((uint32_t)j - s_lo[dg]);
             kd[pos] = key;
-            vd[pos] = val;
+            vd[pos] = s_val[j];
         }
     }
 }

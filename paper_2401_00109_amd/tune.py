@@ -28,7 +28,7 @@ COMPRESS_SPACE = [
     for wpb in (1, 2, 4)
     for bpc in (2, 4, 8, 16)
 ]
-STAGE1_SPACE = [1, 2, 4, 8]
+STAGE1_SPACE = [1, 2, 4]  # larger values are clamped to 4 by the library
 
 
 def shape_key(device, n_series: int, total_points: int, D: int) -> str:

@@ -373,6 +373,21 @@ def test_encode_large_and_tied_dictionaries(k):
     np.testing.assert_array_equal(got, exp)
 
 
+@pytest.mark.parametrize("k", [3, 300, 3000])
+def test_encode_one_column_with_signed_zeros(k):
+    # scl = 0 puts every piece at x = 0; the centers' cx mixes +0.0 and -0.0
+    # (one column), with repeated cy values and exact duplicates
+    rng = np.random.default_rng(100 + k)
+    cx = np.where(rng.random(k) < 0.5, 0.0, -0.0)
+    cy = np.round(rng.standard_normal(k), 1)
+    ln = rng.integers(1, 9, 5000).astype(np.int32)
+    inc = np.round(rng.standard_normal(5000), 2)
+    say(f"encode one column k={k}")
+    got = _gpu_encode(ln, inc, 1.0, 1.0, 0.0, cx, cy)
+    exp = O.encode(ln, inc, 1.0, 1.0, 0.0, cx, cy)
+    np.testing.assert_array_equal(got, exp)
+
+
 def test_encode_equidistant_ties():
     # queries exactly halfway between two centers (dyadic values: exact distances)
     cx = np.array([1.0, 1.0, 2.0, 0.0, 1.5])
