@@ -47,25 +47,25 @@ def log(msg: str) -> None:
 def algorithmic_bytes(name: str, n, N, G, k, nh, active_sort_passes, sort_launches):
     if name.startswith("k_compress"):
         return 8.0 * n + 12.0 * N          # read every point once, write (len, inc)
-    if name == "k_scatter":               # 12 B in + 12 B out per pair, active passes only
+    if name == "k_onesweep":              # 12 B in + 12 B out per pair, active passes only
         return 24.0 * N * active_sort_passes / max(sort_launches, 1)
-    if name == "k_tile_hist":
-        return 8.0 * N * active_sort_passes / max(sort_launches, 1)
     if name == "k_stage1":
-        return 44.0 * N + 24.0 * G         # sorted key,x,y,len,inc in; label, flag out; partials
-    if name == "k_stage2":
-        return 56.0 * G + 24.0 * k
+        return 32.0 * N + 8.0 * G          # sorted key, x, y in; label, flag out; start tags, list
+    if name == "k_block_sums":
+        return 20.0 * N + 24.0 * G         # label, start index, len, inc in; sums out
+    if name == "k_col_greedy":
+        return 56.0 * G
     if name == "k_gather":
-        return 64.0 * N                    # perm, key, random (len, inc) in; 5 sorted arrays out
-    if name == "k_encode":
+        return 68.0 * N                    # perm, key, random 16-byte record in; 5 sorted arrays out
+    if name == "k_key":
+        return 40.0 * N                    # len, inc in; key, index, record out
+    if name == "k_encode" or name.startswith("k_encode<"):
         return 16.0 * N
     if name == "k_recon":
         return 12.0 * N + 8.0 * nh
     if name == "k_remap":
         return 24.0 * N
     if name == "k_compact":
-        return 24.0 * N
-    if name == "k_key":
         return 24.0 * N
     if name.startswith("k_sum_leaves"):
         return 12.0 * N
@@ -213,7 +213,7 @@ def main() -> int:
     n_hat = int(rec.out_off[-1].item())
     dom_name = max(rep, key=lambda n: rep[n][0])
     dom_ms, dom_launches = rep[dom_name]
-    sort_launches = rep.get("k_scatter", (0, 1))[1] / args.steps
+    sort_launches = rep.get("k_onesweep", (0, 1))[1] / args.steps
     alg = algorithmic_bytes(dom_name, w.n_points, N, G, k, n_hat, active_passes, sort_launches)
     roofline = None
     if alg is not None and dom_launches > 0:

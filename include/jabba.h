@@ -55,7 +55,8 @@ enum jabba_status {
     JABBA_OK = 0,
     JABBA_EINVAL = -1,      /* bad argument (sizes, tolerances, null pointers)          */
     JABBA_ENOMEM = -2,      /* workspace smaller than the size query returned            */
-    JABBA_EHIP = -3,        /* a HIP runtime call failed                                 */
+    JABBA_EHIP = -3,        /* a HIP runtime call failed (or, from jabba_workspace_status,
+                               a bounded device-side wait ran out)                       */
     JABBA_ECAPACITY = -4,   /* device: more symbols than the dictionary capacity         */
     JABBA_ENONFINITE = -5,  /* device: a series value is NaN or infinite                 */
     JABBA_EOVERFLOW = -6,   /* a count exceeds the 2^31 limit                            */

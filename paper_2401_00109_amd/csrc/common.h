@@ -17,6 +17,7 @@ enum : int32_t {
     kStCapacity = 2,
     kStOverflow = 4,
     kStInvalid = 8,
+    kStInternal = 16,  // a bounded device-side wait ran out
 };
 
 // ---------------------------------------------------------------- host side
@@ -89,6 +90,13 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int ffs64(uint64_t m) { return m ? __builtin_ctzll(m) : -1; }
 
+// value of lane l (l uniform across the wavefront): two scalar reads, no LDS
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src); }
 __device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) { return __shfl(v, src); }
 __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src); }
@@ -147,10 +155,13 @@ int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
 struct SortBuffers {
     uint64_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *hist;      // 256 * n_tiles_max
-    uint32_t *ghist;     // 8 * 256
-    int32_t *ctl;        // [0] = current buffer, [1..8] = skip flags
-    void *scan_ws;
+    uint64_t *status;    // look-back words, 256 per tile
+    int64_t n_status;
+    uint32_t *ghist;     // 8 * 256 global digit histograms
+    uint32_t *gbase;     // 8 * 256 bucket bases
+    int32_t *tile_ctr;   // tile tickets, one counter per pass
+    int32_t *ctl;        // [0] = buffer with the sorted order, [1..8] = skip flags,
+                         // [9..16] = buffer each pass reads, [32] = look-back error
 };
 size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b);
 // Resets the control words and the global digit histograms.

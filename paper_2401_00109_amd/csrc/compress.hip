@@ -485,10 +485,12 @@ int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, cons
 
 }  // namespace
 
-// defaults (the autotuner may pick others; results never change)
-constexpr int kDefaultW = 4;
-constexpr int kDefaultWavesPerBlock = 4;
-constexpr int kDefaultBlocksPerCu = 8;
+// defaults (the autotuner may pick others; results never change).  One lane
+// per domain keeps 64 domains per wavefront: with short pieces most rounds
+// end a piece, so wider groups mostly test candidates past the first failure.
+constexpr int kDefaultW = 1;
+constexpr int kDefaultWavesPerBlock = 2;
+constexpr int kDefaultBlocksPerCu = 4;
 
 }  // namespace jabba
 
@@ -572,6 +574,8 @@ extern "C" int jabba_workspace_status(const void *workspace, void *stream, int32
         *status = JABBA_EOVERFLOW;
     else if (bits & kStInvalid)
         *status = JABBA_EINVAL;
+    else if (bits & kStInternal)
+        *status = JABBA_EHIP;
     else
         *status = JABBA_OK;
     return JABBA_OK;

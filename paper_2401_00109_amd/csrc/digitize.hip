@@ -224,6 +224,7 @@ __global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds,
         int64_t act = 0;
         for (int d = 0; d < 8; ++d) act += ctl[1 + d] ? 0 : 1;
         ds->sort_passes = act;
+        if (ctl[32]) set_status(ds->status, kStInternal);  // a radix look-back wait ran out
     }
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t c = vs[p];
@@ -366,7 +367,7 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
             if (b0 < c1) {
                 // list entries that left the LDS mirror are read back from memory
                 if (A.head < A.first_cached()) __threadfence();
-                A.expire(__shfl(kq, 0), alpha, key);
+                A.expire(readlane_f64(kq, 0), alpha, key);
                 bool open = inr;
                 int i = A.head;
                 const int fc = A.first_cached();
@@ -395,7 +396,7 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                 uint64_t pend = ballot(open);
                 while (pend) {
                     const int l = ffs64(pend);
-                    const double kl = __shfl(kq, l), xl = __shfl(xq, l), yl = __shfl(yq, l);
+                    const double kl = readlane_f64(kq, l), xl = readlane_f64(xq, l), yl = readlane_f64(yq, l);
                     const int32_t pl = (int32_t)(b0 + l);
                     if (lane == l) {
                         owner = pl;
@@ -474,27 +475,28 @@ __global__ void k_col_keys(const int64_t *__restrict__ g_count, const int32_t *_
             col = slen[spos[g]];
             if (col > kLenCap) col = kLenCap;
         }
-        keys[g] = ((uint64_t)col << 32) | (uint64_t)g;
+        keys[g] = (uint64_t)col;  // stable sort: equal columns keep g order
         vals[g] = (uint32_t)g;
     }
 }
 
 // group cut flags over the column-sorted order, and the gathered coordinates
 __global__ void k_col_cuts(const int64_t *__restrict__ g_count, const uint64_t *__restrict__ k0,
-                           const uint64_t *__restrict__ k1, const int32_t *__restrict__ ctl,
+                           const uint64_t *__restrict__ k1, const uint32_t *__restrict__ v0,
+                           const uint32_t *__restrict__ v1, const int32_t *__restrict__ ctl,
                            const double *__restrict__ gk, const double *__restrict__ gx, const double *__restrict__ gy,
                            double alpha, uint32_t *__restrict__ cut, int32_t *__restrict__ ord,
                            double *__restrict__ ck, double *__restrict__ cx, double *__restrict__ cy) {
     const int64_t G = *g_count;
-    const uint64_t *keys = ctl[0] ? k1 : k0;
+    const uint64_t *keys = ctl[0] ? k1 : k0;  // column
+    const uint32_t *vals = ctl[0] ? v1 : v0;  // starting point
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t kj = keys[j];
-        const int32_t g = (int32_t)(kj & 0xffffffffull);
+        const int32_t g = (int32_t)vals[j];
         bool c = j == 0;
         if (!c) {
-            const uint64_t kp = keys[j - 1];
-            const int32_t gp = (int32_t)(kp & 0xffffffffull);
-            c = (kj >> 32) != (kp >> 32) || !(gk[g] - gk[gp] <= alpha);
+            const int32_t gp = (int32_t)vals[j - 1];
+            c = kj != keys[j - 1] || !(gk[g] - gk[gp] <= alpha);
         }
         cut[j] = c ? 1u : 0u;
         ord[j] = g;
@@ -987,7 +989,8 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     if (rc) return rc;
     rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups");
     if (rc) return rc;
-    JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.ctl, w.gk,
+    JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
+              w.sb.vals[1], w.sb.ctl, w.gk,
               w.gx, w.gy, alpha, w.cut, w.ord, w.ck, w.cx, w.cy);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.cut, w.cgid, w.g_count, N, w.scan_ws, st);

@@ -155,12 +155,6 @@ struct ReconChunk {
     double vin;          // V before the chunk's first piece
 };
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
 constexpr int kReconThreads = 128;
 constexpr int kFillThreads = kReconThreads - kWave;
 

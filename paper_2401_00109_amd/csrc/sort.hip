@@ -5,13 +5,18 @@
 // order) and values are canonical piece indices, so equal keys keep the
 // canonical order.
 //
-// Per pass: tile histograms (digit-major, 256 x tiles) -> exclusive scan ->
-// stable scatter.  Inside a tile the elements are ranked in index order:
-// wavefront peers with the same digit are found with eight ballots, waves
-// are ordered through LDS counters, and rounds of 256 elements follow each
-// other; the ranked tile is staged in LDS and leaves in digit order.  A digit that is the same for every key is skipped; the decision is
-// taken on the device from the global digit histograms, and the buffer that
-// holds the current order is tracked in device memory (ctl[0]), so no host
+// One kernel per digit ("one sweep"): the global histograms of all eight
+// digits are taken once, up front; a pass takes tiles in ticket order, counts
+// the tile's digits, and finds the tile's offset inside each digit bucket by
+// decoupled look-back over the earlier tiles' published counts (each status
+// word carries the pass tag, an aggregate/prefix flag and the count).  Inside
+// a tile each wavefront ranks its own contiguous quarter in index order
+// (peers with the same digit by eight ballots, a running count per digit in
+// the wave's LDS row), and the quarters are ordered by per-digit offsets; the
+// ranked tile is staged in LDS and leaves in digit order, so each digit's run
+// of the tile is one contiguous, coalesced stretch of the destination.  A digit that is the
+// same for every key is skipped; the decision and the buffer parity of every
+// pass are taken on the device from the global histograms, so no host
 // read-back is needed and the sort can be captured in a HIP graph.
 #include "common.h"
 
@@ -23,14 +28,34 @@ constexpr int kThreads = 256;
 constexpr int kRounds = 16;
 constexpr int kTileN = kThreads * kRounds;
 
+// control words
+constexpr int kCtlFinal = 0;   // buffer holding the sorted order after all passes
+constexpr int kCtlSkip = 1;    // [1..8]: digit d is the same for every key
+constexpr int kCtlSrc = 9;     // [9..16]: buffer pass d reads
+constexpr int kCtlError = 32;  // a look-back wait ran out (never expected)
+
+// status word: [63:56] pass tag, [55:54] flag, [31:0] count
+constexpr uint64_t kFlagAgg = 1ull << 54;
+constexpr uint64_t kFlagPre = 2ull << 54;
+constexpr uint64_t kCountMask = 0xffffffffull;
+constexpr int kSpinLimit = 1 << 22;
+
 __device__ __forceinline__ int64_t live(const int64_t *n_dev, int64_t n_max) {
     int64_t n = *n_dev;
     return n < 0 ? 0 : (n > n_max ? n_max : n);
 }
 
-__global__ void k_sort_init(int32_t *ctl, uint32_t *ghist) {
-    if (threadIdx.x == 0) ctl[0] = 0;
+__device__ __forceinline__ int64_t n_tiles(int64_t n) { return (n + kTileN - 1) / kTileN; }
+
+__global__ void k_sort_init(int32_t *ctl, uint32_t *ghist, int32_t *tile_ctr) {
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) ctl[i] = 0;
+    for (int i = threadIdx.x; i < 8; i += blockDim.x) tile_ctr[i] = 0;
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) ghist[i] = 0;
+}
+
+__global__ void k_status_clear(uint64_t *__restrict__ status, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        status[i] = 0;
 }
 
 // Global histograms of all eight digits.
@@ -52,38 +77,6 @@ __global__ __launch_bounds__(kThreads) void k_global_hist(const uint64_t *__rest
     }
 }
 
-// skip[d] = every key has the same digit d
-__global__ void k_plan(const uint32_t *__restrict__ ghist, const int64_t *n_dev, int64_t n_max, int32_t *ctl) {
-    const int d = threadIdx.x / 64;
-    const int lane = threadIdx.x & 63;
-    if (d >= 8) return;
-    const int64_t n = live(n_dev, n_max);
-    bool full = false;
-    for (int b = lane; b < 256; b += 64) full |= (int64_t)ghist[d * 256 + b] == n;
-    uint64_t m = __ballot(full);
-    if (lane == 0) ctl[1 + d] = (m != 0ull || n <= 1) ? 1 : 0;
-}
-
-template <int Tag>
-__global__ __launch_bounds__(kThreads) void k_tile_hist(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
-                                                        const int64_t *n_dev, int64_t n_max, int64_t tiles_max,
-                                                        int shift, const int32_t *ctl, int pass,
-                                                        uint32_t *__restrict__ hist) {
-    if (ctl[1 + pass]) return;
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t *keys = ctl[0] ? k1 : k0;
-    const int64_t n = live(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kTileN;
-    for (int r = 0; r < kRounds; ++r) {
-        int64_t i = base + r * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
-    }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * tiles_max + blockIdx.x] = h[threadIdx.x];
-}
-
 // Exclusive scan of one value per thread over the 256 threads of the block.
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_wave) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -98,66 +91,99 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
     __syncthreads();
     uint32_t add = 0;
     for (int q = 0; q < w; ++q) add += s_wave[q];
+    __syncthreads();
     return x - v + add;
 }
 
-// Stable scatter of one tile.  The tile is first ranked into LDS in digit
-// order (the rank of an element is its position among the tile's elements
-// with the same digit, in index order), then written out in that order, so
-// each digit's run of the tile lands in one contiguous stretch of the
-// destination and the stores of consecutive threads are coalesced.
+// Per digit: skip flag, bucket bases (exclusive scan of the global
+// histogram), and the buffer each pass reads.  One workgroup of 256.
+__global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ ghist, const int64_t *n_dev,
+                                                   int64_t n_max, int32_t *ctl, uint32_t *__restrict__ gbase) {
+    __shared__ uint32_t s_wave[kThreads / kWave];
+    __shared__ int s_full;
+    const int64_t n = live(n_dev, n_max);
+    int active = 0;
+    for (int d = 0; d < 8; ++d) {
+        if (threadIdx.x == 0) s_full = 0;
+        __syncthreads();
+        const uint32_t c = ghist[d * 256 + threadIdx.x];
+        if ((int64_t)c == n) s_full = 1;
+        gbase[d * 256 + threadIdx.x] = block_excl_scan_256(c, s_wave);
+        const bool skip = s_full != 0 || n <= 1;
+        if (threadIdx.x == 0) {
+            ctl[kCtlSkip + d] = skip ? 1 : 0;
+            ctl[kCtlSrc + d] = active & 1;
+        }
+        active += skip ? 0 : 1;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl[kCtlFinal] = active & 1;
+}
+
 template <int Tag>
-__global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
-                                                      uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
-                                                      const int64_t *n_dev, int64_t n_max, int64_t tiles_max, int shift,
-                                                      const int32_t *ctl, int pass,
-                                                      const uint32_t *__restrict__ offs) {
-    if (ctl[1 + pass]) return;
+__global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
+                                                       uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
+                                                       const int64_t *n_dev, int64_t n_max, int shift, int32_t *ctl,
+                                                       int pass, const uint32_t *__restrict__ gbase,
+                                                       uint64_t *__restrict__ status, int32_t *__restrict__ tile_ctr) {
+    if (ctl[kCtlSkip + pass]) return;
+    constexpr int kWaves = kThreads / kWave;
+    constexpr int kPerWave = kTileN / kWaves;  // contiguous quarter of the tile per wavefront
     __shared__ uint64_t s_key[kTileN];
     __shared__ uint32_t s_val[kTileN];
-    __shared__ uint32_t s_run[256];  // next free local slot per digit
-    __shared__ uint32_t s_lo[256];   // local start per digit
-    __shared__ uint32_t s_go[256];   // destination start per digit
-    __shared__ uint32_t s_cnt[kThreads / kWave][256];
-    __shared__ uint32_t s_pre[kThreads / kWave][256];
-    __shared__ uint32_t s_wave[kThreads / kWave];
+    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_lo[256];          // local start per digit
+    __shared__ uint32_t s_go[256];          // destination start per digit
+    __shared__ uint32_t s_wrun[kWaves][256];  // per-wave count, then per-wave offset, per digit
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ int64_t s_tile;
     const int tid = threadIdx.x;
     const int w = tid / kWave;
-    const bool src1 = ctl[0] != 0;
+    const int lane = tid & (kWave - 1);
+    if (tid == 0) s_tile = atomicAdd(&tile_ctr[pass], 1);
+    s_hist[tid] = 0;
+    for (int q = 0; q < kWaves; ++q) s_wrun[q][tid] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t n = live(n_dev, n_max);
+    const int64_t base = tile * kTileN;
+    if (base >= n) return;
+    const bool src1 = ctl[kCtlSrc + pass] != 0;
     const uint64_t *ks = src1 ? k1 : k0;
     const uint32_t *vs = src1 ? v1 : v0;
     uint64_t *kd = src1 ? k0 : k1;
     uint32_t *vd = src1 ? v0 : v1;
-    const int64_t n = live(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kTileN;
-    if (base >= n) return;
     const int m = (int)(n - base < kTileN ? n - base : kTileN);
 
-    // all of this thread's elements in flight at once
+    // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
+    // (wave, round, lane) order is index order; all loads in flight at once
     uint64_t kr[kRounds];
     uint32_t vr[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        const int li = r * kThreads + tid;
+        const int li = w * kPerWave + r * kWave + lane;
         kr[r] = li < m ? ks[base + li] : 0ull;
         vr[r] = li < m ? vs[base + li] : 0u;
     }
-    // this tile's count of digit `tid`: difference of consecutive scanned
-    // offsets (digit-major layout; the entry after the last is the total)
-    const uint32_t g0 = offs[(int64_t)tid * tiles_max + blockIdx.x];
-    const uint32_t g1 = offs[(int64_t)tid * tiles_max + blockIdx.x + 1];
-    const uint32_t lo = block_excl_scan_256(g1 - g0, s_wave);
-    s_lo[tid] = lo;
-    s_run[tid] = lo;
-    s_go[tid] = g0;
-    for (int i = 0; i < kThreads / kWave; ++i) s_cnt[i][tid] = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+        if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[(uint32_t)(kr[r] >> shift) & 255u], 1u);
     __syncthreads();
+    const uint32_t cnt = s_hist[tid];
+
+    // publish this tile's counts early, so later tiles' look-backs find them
+    const uint64_t tag = (uint64_t)(pass + 1) << 56;
+    __hip_atomic_store(&status[tile * 256 + tid], tag | (tile == 0 ? kFlagPre : kFlagAgg) | cnt, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+
+    // wave-local ranking in index order: peers with the same digit by eight
+    // ballots, a running count per digit in this wave's LDS row
+    uint32_t wpos[kRounds];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        const bool ok = r * kThreads + tid < m;
-        const uint64_t key = kr[r];
-        const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        const bool ok = w * kPerWave + r * kWave + lane < m;
+        const uint32_t dg = (uint32_t)(kr[r] >> shift) & 255u;
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -166,26 +192,57 @@ __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0,
             peers &= bit ? bb : ~bb;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (ok && rank == 0) s_cnt[w][dg] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {
-            uint32_t run = s_run[tid];
-#pragma unroll
-            for (int q = 0; q < kThreads / kWave; ++q) {
-                s_pre[q][tid] = run;
-                run += s_cnt[q][tid];
-                s_cnt[q][tid] = 0;
+        const uint32_t run = s_wrun[w][dg];
+        wpos[r] = run + rank;
+        if (ok && rank == 0) s_wrun[w][dg] = run + (uint32_t)__popcll(peers);
+    }
+
+    // look-back: this tile's offset inside bucket `tid`
+    uint64_t excl = 0;
+    if (tile > 0) {
+        int64_t t = tile - 1;
+        int spins = 0;
+        while (t >= 0) {
+            const uint64_t v = __hip_atomic_load(&status[t * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((v >> 56) != (uint64_t)(pass + 1) || (v & (kFlagAgg | kFlagPre)) == 0) {
+                if (++spins > kSpinLimit) {  // cannot happen while every earlier tile runs; bail out loudly
+                    __hip_atomic_store(&ctl[kCtlError], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
             }
-            s_run[tid] = run;
+            excl += v & kCountMask;
+            if (v & kFlagPre) break;
+            --t;
         }
-        __syncthreads();
-        if (ok) {
-            const uint32_t lp = s_pre[w][dg] + rank;
-            s_key[lp] = key;
+        __hip_atomic_store(&status[tile * 256 + tid], tag | kFlagPre | ((excl + cnt) & kCountMask), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();  // every wave's counts are final
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            const uint32_t c = s_wrun[q][tid];
+            s_wrun[q][tid] = acc;
+            acc += c;
+        }
+    }
+    s_lo[tid] = block_excl_scan_256(cnt, s_wave);
+    s_go[tid] = gbase[pass * 256 + tid] + (uint32_t)excl;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (w * kPerWave + r * kWave + lane < m) {
+            const uint32_t dg = (uint32_t)(kr[r] >> shift) & 255u;
+            const uint32_t lp = s_lo[dg] + s_wrun[w][dg] + wpos[r];
+            s_key[lp] = kr[r];
             s_val[lp] = vr[r];
         }
     }
     __syncthreads();
+    // leave in digit order: consecutive slots of one digit are consecutive destinations
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int j = r * kThreads + tid;
@@ -199,10 +256,6 @@ __global__ __launch_bounds__(kThreads) void k_scatter(uint64_t *__restrict__ k0,
     }
 }
 
-__global__ void k_flip(int32_t *ctl, int pass) {
-    if (threadIdx.x == 0 && !ctl[1 + pass]) ctl[0] ^= 1;
-}
-
 }  // namespace
 
 size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b) {
@@ -212,16 +265,23 @@ size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b) {
     x.keys[1] = c.take<uint64_t>(n_max);
     x.vals[0] = c.take<uint32_t>(n_max);
     x.vals[1] = c.take<uint32_t>(n_max);
-    x.hist = c.take<uint32_t>(256 * tiles + 1);
+    x.status = c.take<uint64_t>(256 * tiles);
+    x.n_status = 256 * tiles;
     x.ghist = c.take<uint32_t>(8 * 256);
+    x.gbase = c.take<uint32_t>(8 * 256);
+    x.tile_ctr = c.take<int32_t>(8);
     x.ctl = c.take<int32_t>(64);
-    x.scan_ws = c.take<char>(scan_workspace(256 * tiles));
     if (b) *b = x;
     return c.bytes();
 }
 
 int radix_sort_init(const SortBuffers &b, hipStream_t st) {
-    JB_LAUNCH(k_sort_init, dim3(1), dim3(256), 0, st, b.ctl, b.ghist);
+    JB_LAUNCH(k_sort_init, dim3(1), dim3(256), 0, st, b.ctl, b.ghist, b.tile_ctr);
+    JB_LAUNCH_CHECK();
+    int64_t blocks = (b.n_status + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 8;
+    if (blocks > cap) blocks = cap;
+    JB_LAUNCH(k_status_clear, dim3((unsigned)blocks), dim3(256), 0, st, b.status, b.n_status);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -231,8 +291,7 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
     int cap = device_cu_count() * 8;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    JB_LAUNCH(k_global_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, b.keys[0], n_dev, n_max,
-                       b.ghist);
+    JB_LAUNCH(k_global_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, b.keys[0], n_dev, n_max, b.ghist);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -240,23 +299,12 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag) {
     const bool main_sort = !tag || !tag[0];
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
-    JB_LAUNCH(k_plan, dim3(1), dim3(512), 0, st, b.ghist, n_dev, n_max, b.ctl);
+    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, b.ctl, b.gbase);
     JB_LAUNCH_CHECK();
     for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 8 * pass;
-        JB_LAUNCH_NAMED(main_sort ? "k_tile_hist" : "k_tile_hist_groups",
-                        main_sort ? k_tile_hist<0> : k_tile_hist<1>, dim3((unsigned)tiles),
-                        dim3(kThreads), 0, st, b.keys[0], b.keys[1], n_dev,
-                           n_max, tiles, shift, b.ctl, pass, b.hist);
-        JB_LAUNCH_CHECK();
-        int rc = scan_u32_to_u32(b.hist, b.hist, nullptr, 256 * tiles, b.scan_ws, st);
-        if (rc) return rc;
-        JB_LAUNCH_NAMED(main_sort ? "k_scatter" : "k_scatter_groups",
-                        main_sort ? k_scatter<0> : k_scatter<1>, dim3((unsigned)tiles),
-                        dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0],
-                           b.vals[1], n_dev, n_max, tiles, shift, b.ctl, pass, b.hist);
-        JB_LAUNCH_CHECK();
-        JB_LAUNCH(k_flip, dim3(1), dim3(64), 0, st, b.ctl, pass);
+        JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups", main_sort ? k_onesweep<0> : k_onesweep<1>,
+                        dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0], b.vals[1],
+                        n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.status, b.tile_ctr);
         JB_LAUNCH_CHECK();
     }
     return JABBA_OK;

@@ -45,7 +45,7 @@ def timing_name(kernel: str) -> str:
     base, targs = m.group(1), (m.group(2) or "")
     if base == "k_compress":
         return "k_compress<W>"
-    if base in ("k_scatter", "k_tile_hist"):
+    if base == "k_onesweep":
         return base + ("_groups" if targs == "<1>" else "")
     return base + targs
 
