@@ -160,6 +160,7 @@ struct SortBuffers {
     uint32_t *ghist;     // 8 * 256 global digit histograms
     uint32_t *gbase;     // 8 * 256 bucket bases
     int32_t *tile_ctr;   // tile tickets, one counter per pass
+    unsigned long long *kmin;  // smallest key; digits are taken from key - kmin
     int32_t *ctl;        // [0] = buffer with the sorted order, [1..8] = skip flags,
                          // [9..16] = buffer each pass reads, [32] = look-back error
 };

@@ -129,7 +129,7 @@ struct RingShape {
 
 template <int W>
 size_t compress_lds_per_wave() {
-    return (size_t)(kWave / W) * RingShape<W>::R * sizeof(double);
+    return (size_t)(kWave / W) * (RingShape<W>::R + 1) * sizeof(double);
 }
 
 template <int W>
@@ -147,7 +147,10 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     const int j = lane & (W - 1);
     const int leader = lane - j;
     const uint64_t gmask = (W == 64) ? ~0ull : (((1ull << W) - 1ull) << leader);
-    double *ring = ring_all + (size_t)(threadIdx.x / kWave) * (kWave / W) * R + (size_t)(lane / W) * R;
+    // one ring per group; the stride of R + 1 doubles puts the same slot of
+    // neighbouring groups in different LDS banks (domains of equal length
+    // keep their groups' slots in step)
+    double *ring = ring_all + ((size_t)(threadIdx.x / kWave) * (kWave / W) + (size_t)(lane / W)) * (R + 1);
     const int64_t n_dom = *n_dom_p;
     const bool direct = direct_base >= 0;
     const int64_t wave_g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;

@@ -382,12 +382,27 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                     }
                 }
                 if (i >= fc) {
-                    for (; i < A.tail; ++i) {
+                    // kGroup starts per step: their loads issue together, the
+                    // tests run in list order, one ballot per step
+                    constexpr int kGroup = 4;
+                    for (; i < A.tail; i += kGroup) {
                         if (ballot(open) == 0ull) break;
-                        const int e = i % kActCap;
-                        if (open && covers(kq, xq, yq, L->k[e], L->x[e], L->y[e], alpha, a2)) {
-                            owner = L->p[e];
-                            open = false;
+                        double gk[kGroup], gx[kGroup], gy[kGroup];
+                        int32_t gp[kGroup];
+#pragma unroll
+                        for (int u = 0; u < kGroup; ++u) {
+                            const int e = (i + u) & (kActCap - 1);
+                            gk[u] = L->k[e];
+                            gx[u] = L->x[e];
+                            gy[u] = L->y[e];
+                            gp[u] = L->p[e];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kGroup; ++u) {
+                            if (open && i + u < A.tail && covers(kq, xq, yq, gk[u], gx[u], gy[u], alpha, a2)) {
+                                owner = gp[u];
+                                open = false;
+                            }
                         }
                     }
                 }

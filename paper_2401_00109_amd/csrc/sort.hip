@@ -47,7 +47,8 @@ __device__ __forceinline__ int64_t live(const int64_t *n_dev, int64_t n_max) {
 
 __device__ __forceinline__ int64_t n_tiles(int64_t n) { return (n + kTileN - 1) / kTileN; }
 
-__global__ void k_sort_init(int32_t *ctl, uint32_t *ghist, int32_t *tile_ctr) {
+__global__ void k_sort_init(int32_t *ctl, uint32_t *ghist, int32_t *tile_ctr, unsigned long long *kmin) {
+    if (threadIdx.x == 0) *kmin = ~0ull;
     for (int i = threadIdx.x; i < 64; i += blockDim.x) ctl[i] = 0;
     for (int i = threadIdx.x; i < 8; i += blockDim.x) tile_ctr[i] = 0;
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) ghist[i] = 0;
@@ -58,15 +59,50 @@ __global__ void k_status_clear(uint64_t *__restrict__ status, int64_t n) {
         status[i] = 0;
 }
 
-// Global histograms of all eight digits.
+// Smallest key.  The passes sort key - kmin, which has the same order and,
+// for keys spanning less than 2^56, a constant top digit (one pass fewer).
+__global__ __launch_bounds__(1024) void k_key_min(const uint64_t *__restrict__ keys, const int64_t *n_dev,
+                                                  int64_t n_max, unsigned long long *__restrict__ kmin) {
+    __shared__ unsigned long long s_min[1024 / kWave];
+    const int64_t n = live(n_dev, n_max);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long m = ~0ull;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {  // four loads in flight
+        const unsigned long long a = keys[i], b = keys[i + stride], c = keys[i + 2 * stride],
+                                 d = keys[i + 3 * stride];
+        const unsigned long long ab = a < b ? a : b, cd = c < d ? c : d;
+        const unsigned long long x = ab < cd ? ab : cd;
+        m = x < m ? x : m;
+    }
+    for (; i < n; i += stride) {
+        const unsigned long long k = keys[i];
+        m = k < m ? k : m;
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned long long y = __shfl_xor(m, o);
+        m = y < m ? y : m;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) s_min[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) m = s_min[w] < m ? s_min[w] : m;
+        if (m != ~0ull) atomicMin(kmin, m);  // one atomic per workgroup
+    }
+}
+
+// Global histograms of all eight digits of key - kmin.
 __global__ __launch_bounds__(kThreads) void k_global_hist(const uint64_t *__restrict__ keys, const int64_t *n_dev,
-                                                          int64_t n_max, uint32_t *__restrict__ ghist) {
+                                                          int64_t n_max, const unsigned long long *__restrict__ kmin,
+                                                          uint32_t *__restrict__ ghist) {
     __shared__ uint32_t h[8][256];
     for (int i = threadIdx.x; i < 8 * 256; i += kThreads) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t n = live(n_dev, n_max);
+    const uint64_t k0 = *kmin;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        uint64_t k = keys[i];
+        uint64_t k = keys[i] - k0;
 #pragma unroll
         for (int d = 0; d < 8; ++d) atomicAdd(&h[d][(k >> (8 * d)) & 255], 1u);
     }
@@ -125,6 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
                                                        uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
                                                        const int64_t *n_dev, int64_t n_max, int shift, int32_t *ctl,
                                                        int pass, const uint32_t *__restrict__ gbase,
+                                                       const unsigned long long *__restrict__ kmin,
                                                        uint64_t *__restrict__ status, int32_t *__restrict__ tile_ctr) {
     if (ctl[kCtlSkip + pass]) return;
     constexpr int kWaves = kThreads / kWave;
@@ -154,6 +191,8 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
     uint64_t *kd = src1 ? k0 : k1;
     uint32_t *vd = src1 ? v0 : v1;
     const int m = (int)(n - base < kTileN ? n - base : kTileN);
+    const uint64_t kbase = *kmin;
+    auto digit = [&](uint64_t key) -> uint32_t { return (uint32_t)((key - kbase) >> shift) & 255u; };
 
     // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
     // (wave, round, lane) order is index order; all loads in flight at once
@@ -167,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
     }
 #pragma unroll
     for (int r = 0; r < kRounds; ++r)
-        if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[(uint32_t)(kr[r] >> shift) & 255u], 1u);
+        if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[digit(kr[r])], 1u);
     __syncthreads();
     const uint32_t cnt = s_hist[tid];
 
@@ -183,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const bool ok = w * kPerWave + r * kWave + lane < m;
-        const uint32_t dg = (uint32_t)(kr[r] >> shift) & 255u;
+        const uint32_t dg = digit(kr[r]);
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -197,24 +236,40 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
         if (ok && rank == 0) s_wrun[w][dg] = run + (uint32_t)__popcll(peers);
     }
 
-    // look-back: this tile's offset inside bucket `tid`
+    // look-back: this tile's offset inside bucket `tid`.  The status words of
+    // kWindow earlier tiles are read together; they are consumed newest
+    // first until a prefix is found, waiting only on words not yet published.
     uint64_t excl = 0;
     if (tile > 0) {
+        constexpr int kWindow = 8;
+        const uint64_t ready_tag = (uint64_t)(pass + 1);
         int64_t t = tile - 1;
         int spins = 0;
-        while (t >= 0) {
-            const uint64_t v = __hip_atomic_load(&status[t * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((v >> 56) != (uint64_t)(pass + 1) || (v & (kFlagAgg | kFlagPre)) == 0) {
-                if (++spins > kSpinLimit) {  // cannot happen while every earlier tile runs; bail out loudly
-                    __hip_atomic_store(&ctl[kCtlError], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+        bool done = false;
+        while (!done) {
+            uint64_t v[kWindow];
+#pragma unroll
+            for (int i = 0; i < kWindow; ++i)
+                v[i] = t - i >= 0 ? __hip_atomic_load(&status[(t - i) * 256 + tid], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0ull;  // never consumed: tile 0 always holds a prefix
+#pragma unroll
+            for (int i = 0; i < kWindow; ++i) {
+                if (done) break;
+                uint64_t x = v[i];
+                while ((x >> 56) != ready_tag || (x & (kFlagAgg | kFlagPre)) == 0) {
+                    if (++spins > kSpinLimit) {  // cannot happen while every earlier tile runs; bail out loudly
+                        __hip_atomic_store(&ctl[kCtlError], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        x = ready_tag << 56 | kFlagPre;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    x = __hip_atomic_load(&status[(t - i) * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+                excl += x & kCountMask;
+                if (x & kFlagPre) done = true;
             }
-            excl += v & kCountMask;
-            if (v & kFlagPre) break;
-            --t;
+            t -= kWindow;
         }
         __hip_atomic_store(&status[tile * 256 + tid], tag | kFlagPre | ((excl + cnt) & kCountMask), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -235,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         if (w * kPerWave + r * kWave + lane < m) {
-            const uint32_t dg = (uint32_t)(kr[r] >> shift) & 255u;
+            const uint32_t dg = digit(kr[r]);
             const uint32_t lp = s_lo[dg] + s_wrun[w][dg] + wpos[r];
             s_key[lp] = kr[r];
             s_val[lp] = vr[r];
@@ -248,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
         const int j = r * kThreads + tid;
         if (j < m) {
             const uint64_t key = s_key[j];
-            const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+            const uint32_t dg = digit(key);
             const uint32_t pos = s_go[dg] + ((uint32_t)j - s_lo[dg]);
             kd[pos] = key;
             vd[pos] = s_val[j];
@@ -270,13 +325,14 @@ size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b) {
     x.ghist = c.take<uint32_t>(8 * 256);
     x.gbase = c.take<uint32_t>(8 * 256);
     x.tile_ctr = c.take<int32_t>(8);
+    x.kmin = c.take<unsigned long long>(1);
     x.ctl = c.take<int32_t>(64);
     if (b) *b = x;
     return c.bytes();
 }
 
 int radix_sort_init(const SortBuffers &b, hipStream_t st) {
-    JB_LAUNCH(k_sort_init, dim3(1), dim3(256), 0, st, b.ctl, b.ghist, b.tile_ctr);
+    JB_LAUNCH(k_sort_init, dim3(1), dim3(256), 0, st, b.ctl, b.ghist, b.tile_ctr, b.kmin);
     JB_LAUNCH_CHECK();
     int64_t blocks = (b.n_status + 255) / 256;
     const int64_t cap = (int64_t)device_cu_count() * 8;
@@ -291,7 +347,12 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
     int cap = device_cu_count() * 8;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    JB_LAUNCH(k_global_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, b.keys[0], n_dev, n_max, b.ghist);
+    const int64_t min_blocks = (n_max + 1023) / 1024 < device_cu_count() ? (n_max + 1023) / 1024 : device_cu_count();
+    JB_LAUNCH(k_key_min, dim3((unsigned)(min_blocks < 1 ? 1 : min_blocks)), dim3(1024), 0, st, b.keys[0], n_dev,
+              n_max, b.kmin);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_global_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, b.keys[0], n_dev, n_max, b.kmin,
+              b.ghist);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -304,7 +365,7 @@ int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, 
     for (int pass = 0; pass < 8; ++pass) {
         JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups", main_sort ? k_onesweep<0> : k_onesweep<1>,
                         dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0], b.vals[1],
-                        n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.status, b.tile_ctr);
+                        n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.kmin, b.status, b.tile_ctr);
         JB_LAUNCH_CHECK();
     }
     return JABBA_OK;
