@@ -90,6 +90,14 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int ffs64(uint64_t m) { return m ? __builtin_ctzll(m) : -1; }
 
+// One step of a wavefront scan: the value of a lane selected by a DPP
+// control (row shifts within rows of 16 lanes, row broadcasts across rows);
+// lanes without a source read 0.  Register-to-register, no LDS.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, true);
+}
+
 // value of lane l (l uniform across the wavefront): two scalar reads, no LDS
 __device__ __forceinline__ double readlane_f64(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);

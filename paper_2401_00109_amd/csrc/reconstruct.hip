@@ -24,6 +24,29 @@ __device__ __forceinline__ u128 shfl_up_u128(u128 v, int d) {
     hi = __shfl_up(hi, d);
     return ((u128)hi << 64) | lo;
 }
+// DPP step on the four 32-bit limbs of a u128
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ u128 dpp_u128(u128 v) {
+    const uint32_t a = dpp_u32<Ctrl, RowMask>((uint32_t)v);
+    const uint32_t b = dpp_u32<Ctrl, RowMask>((uint32_t)(v >> 32));
+    const uint32_t c = dpp_u32<Ctrl, RowMask>((uint32_t)(v >> 64));
+    const uint32_t d = dpp_u32<Ctrl, RowMask>((uint32_t)(v >> 96));
+    return ((u128)d << 96) | ((u128)c << 64) | ((u128)b << 32) | (u128)a;
+}
+
+// inclusive scan of a u128 across the 64 lanes (exact integer sums): row
+// shifts by 1, 2, 4, 8 scan each row of 16 lanes, then lane 15 of rows 0 and
+// 2 is added to rows 1 and 3, and lane 31 to rows 2 and 3
+__device__ __forceinline__ u128 wave_incl_scan_u128(u128 x) {
+    x += dpp_u128<0x111, 0xf>(x);
+    x += dpp_u128<0x112, 0xf>(x);
+    x += dpp_u128<0x114, 0xf>(x);
+    x += dpp_u128<0x118, 0xf>(x);
+    x += dpp_u128<0x142, 0xa>(x);
+    x += dpp_u128<0x143, 0xc>(x);
+    return x;
+}
+
 __device__ __forceinline__ u128 shfl_u128(u128 v, int l) {
     unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
     lo = __shfl(lo, l);
@@ -198,13 +221,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
                 if (j + kWave < b) raw_n = src.load(j + kWave, tag_n);
                 tag_n = (j + 2 * kWave < b) ? src.tag(j + 2 * kWave) : 0;
                 // inclusive scan of the fixed-point center lengths
-                u128 C = lt;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const u128 y = shfl_up_u128(C, d);
-                    if (lane >= d) C += y;
-                }
-                C += carryC;
+                u128 C = wave_incl_scan_u128(lt) + carryC;
                 const int64_t S = fixed_round(C);
                 int64_t Sp = __shfl_up(S, 1);
                 if (lane == 0) Sp = carryS;
@@ -215,7 +232,15 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
                 const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
                 ReconChunk &B = buf[t & 1];
                 if (lane == 0) B.vin = V;
-                for (int l = 0; l < cnt; ++l) {
+                int l = 0;
+                for (; l + 4 <= cnt; l += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        V = V + readlane_f64(it, l + u);
+                        B.vme[l + u] = V;
+                    }
+                }
+                for (; l < cnt; ++l) {
                     V = V + readlane_f64(it, l);
                     B.vme[l] = V;
                 }
