@@ -61,8 +61,8 @@ def algorithmic_bytes(name: str, n, N, G, k, nh, active_sort_passes, sort_launch
         return 40.0 * N                    # len, inc in; key, index, record out
     if name == "k_encode" or name.startswith("k_encode<"):
         return 16.0 * N
-    if name == "k_recon":
-        return 12.0 * N + 8.0 * nh
+    if name == "k_recon":                 # symbols, lhat; output points written, originals read for the SSE
+        return 12.0 * N + 16.0 * nh
     if name == "k_remap":
         return 24.0 * N
     if name == "k_compact":

@@ -115,6 +115,35 @@ __global__ void k_prepare(int32_t *status, int32_t *q_head) {
     }
 }
 
+// Lane exchanges inside a group of W lanes.  For W <= 16 they are DPP moves
+// (quad permutations for W <= 4, row shifts for W = 8, 16): register to
+// register, no LDS round trip on the round's critical path.
+template <int Ctrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), Ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), Ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// value of lane (j - O) of the group (only read where j >= O)
+template <int W, int O>
+__device__ __forceinline__ double group_up(double v) {
+    if constexpr (W == 2) return dpp_f64<0xA0>(v);                 // quad_perm(0,0,2,2)
+    else if constexpr (W == 4 && O == 1) return dpp_f64<0x90>(v);  // quad_perm(0,0,1,2)
+    else if constexpr (W == 4 && O == 2) return dpp_f64<0x44>(v);  // quad_perm(0,1,0,1)
+    else if constexpr (W == 8 || W == 16) return dpp_f64<0x110 + O>(v);  // row_shr:O
+    else return __shfl_up(v, O, W);
+}
+
+// value of the group's last lane
+template <int W>
+__device__ __forceinline__ double group_last(double v, int leader) {
+    if constexpr (W == 1) return v;
+    else if constexpr (W == 2) return dpp_f64<0xF5>(v);  // quad_perm(1,1,3,3)
+    else if constexpr (W == 4) return dpp_f64<0xFF>(v);  // quad_perm(3,3,3,3)
+    else return __shfl(v, leader + W - 1);
+}
+
 // Ring of staged points per group (positions p live in slot p & (R - 1)).
 // Small rings keep every group of a launch resident at once (the LDS of a
 // compute unit holds ~160 groups of 64 points); the next Q points are always
@@ -256,14 +285,29 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
             }
             S2 = a2;
             S1 = a1;
-#pragma unroll
-            for (int o = 1; o < W; o <<= 1) {
-                const double y2 = __shfl_up(S2, o, W);
-                const double y1 = __shfl_up(S1, o, W);
-                if (j >= o) {
-                    S2 += y2;
-                    S1 += y1;
-                }
+            if constexpr (W >= 2) {
+                const double y2 = group_up<W, 1>(S2), y1 = group_up<W, 1>(S1);
+                if (j >= 1) { S2 += y2; S1 += y1; }
+            }
+            if constexpr (W >= 4) {
+                const double y2 = group_up<W, 2>(S2), y1 = group_up<W, 2>(S1);
+                if (j >= 2) { S2 += y2; S1 += y1; }
+            }
+            if constexpr (W >= 8) {
+                const double y2 = group_up<W, 4>(S2), y1 = group_up<W, 4>(S1);
+                if (j >= 4) { S2 += y2; S1 += y1; }
+            }
+            if constexpr (W >= 16) {
+                const double y2 = group_up<W, 8>(S2), y1 = group_up<W, 8>(S1);
+                if (j >= 8) { S2 += y2; S1 += y1; }
+            }
+            if constexpr (W >= 32) {
+                const double y2 = group_up<W, 16>(S2), y1 = group_up<W, 16>(S1);
+                if (j >= 16) { S2 += y2; S1 += y1; }
+            }
+            if constexpr (W >= 64) {
+                const double y2 = group_up<W, 32>(S2), y1 = group_up<W, 32>(S1);
+                if (j >= 32) { S2 += y2; S1 += y1; }
             }
             S2 += S2c;
             S1 += S1c;
@@ -287,8 +331,8 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
             }
         }
         const uint64_t fm = ballot(act && verdict < 0) & gmask;
-        const double S2last = __shfl(S2, leader + W - 1);
-        const double S1last = __shfl(S1, leader + W - 1);
+        const double S2last = group_last<W>(S2, leader);
+        const double S1last = group_last<W>(S1, leader);
         if (!act) continue;
         if (fm) {
             // the first rejected candidate ends the piece at the last accepted length

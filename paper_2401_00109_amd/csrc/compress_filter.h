@@ -37,7 +37,15 @@ JB_HD inline int filter_decide(double S2, double S1, double b, double ts, int32_
     const double u = 1.1102230246251565e-16;
     const double cm1 = (double)(c - 1);
     const double cd = (double)c;
-    const double K2 = cm1 * cd * (2.0 * cd - 1.0) / 6.0;
+    // K2 = sum_{k<c} k^2, an exact integer below c = 2^20 (rounded once to
+    // double past 2^53; that relative error u is inside the 8u*ME term)
+    double K2;
+    if (c <= (1 << 20)) {
+        const int64_t ci = c;
+        K2 = (double)((ci - 1) * ci * (2 * ci - 1) / 6);
+    } else {
+        K2 = cm1 * cd * (2.0 * cd - 1.0) / 6.0;
+    }
     const double T1 = (2.0 * b) * S1;
     const double T2 = (b * b) * K2;
     const double E = (S2 - T1) + T2;

@@ -181,10 +181,17 @@ struct ReconChunk {
 constexpr int kReconThreads = 128;
 constexpr int kFillThreads = kReconThreads - kWave;
 
+// With `values`, the filler also accumulates the squared error against the
+// original series over the common prefix m = min(n, n^): each filler thread
+// sums its own points in order, and the 64 partials are added by one fixed
+// tree per series (deterministic).
 __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t *__restrict__ piece_off,
                                                          const int64_t *__restrict__ out_off, int64_t n_series,
                                                          const double *__restrict__ t0, double *__restrict__ out,
-                                                         int64_t *__restrict__ lhat) {
+                                                         int64_t *__restrict__ lhat,
+                                                         const int64_t *__restrict__ series_off,
+                                                         const double *__restrict__ values,
+                                                         double *__restrict__ sse, int64_t *__restrict__ sse_cnt) {
     __shared__ ReconChunk buf[2];
     const int lane = lane_id();
     const bool producer = threadIdx.x < kWave;
@@ -192,6 +199,18 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
         const int64_t a = piece_off[s], b = piece_off[s + 1];
         const int64_t o = out_off[s];
         const int64_t nch = b > a ? (b - a + kWave - 1) / kWave : 0;
+        // squared-error state (filler threads)
+        int64_t m_err = 0, vo = 0;
+        double err = 0.0;
+        if (values && !producer) {
+            vo = series_off[s];
+            const int64_t n = series_off[s + 1] - vo, nh = out_off[s + 1] - o;
+            m_err = n < nh ? n : nh;
+            if (threadIdx.x == kWave && m_err > 0) {
+                const double d = values[vo] - t0[s];
+                err = d * d;
+            }
+        }
         u128 carryC = 0;
         int64_t carryS = 0;
         double V = 0.0;
@@ -268,39 +287,24 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
                             L = M + 1;
                     }
                     const double vprev = L > 0 ? B.vme[L - 1] : B.vin;
-                    out[o + r] = (r == B.end[L]) ? B.vme[L] : vprev + B.slope[L] * (double)(r - B.beg[L]);
+                    const double vr = (r == B.end[L]) ? B.vme[L] : vprev + B.slope[L] * (double)(r - B.beg[L]);
+                    out[o + r] = vr;
+                    if (r < m_err) {
+                        const double d = values[vo + r] - vr;
+                        err = err + d * d;
+                    }
                 }
                 if (lhat)
                     for (int l = f; l < cnt; l += kFillThreads) lhat[j0 + l] = B.end[l] - B.beg[l];
             }
             __syncthreads();
         }
-    }
-}
-
-__global__ __launch_bounds__(256) void k_recon_sse(const int64_t *__restrict__ out_off,
-                                                   const int64_t *__restrict__ series_off, int64_t n_series,
-                                                   const double *__restrict__ values, const double *__restrict__ out,
-                                                   double *__restrict__ sse, int64_t *__restrict__ cnt) {
-    const int lane = lane_id();
-    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
-        const int64_t n = series_off[s + 1] - series_off[s];
-        const int64_t nh = out_off[s + 1] - out_off[s];
-        const int64_t m = n < nh ? n : nh;
-        double acc = 0.0;
-        for (int64_t i0 = 0; i0 < m; i0 += kWave) {
-            const int64_t i = i0 + lane;
-            double v = 0.0;
-            if (i < m) {
-                const double d = values[series_off[s] + i] - out[out_off[s] + i];
-                v = d * d;
+        if (values && !producer) {
+            const double tot = wave_tree_sum(err);
+            if (threadIdx.x == kWave) {
+                sse[s] = tot;
+                sse_cnt[s] = m_err;
             }
-            acc = acc + wave_tree_sum(v);
-        }
-        if (lane == 0) {
-            sse[s] = acc;
-            cnt[s] = m;
         }
     }
 }
@@ -387,15 +391,10 @@ extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_of
     if (!t0 || !out || !series_off) return JABBA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
+    if (values && (!sse || !cnt)) return JABBA_EINVAL;
     JB_LAUNCH(k_recon, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off, out_off, n_series,
-              t0, out, lhat);
+              t0, out, lhat, series_off, values, sse, cnt);
     JB_LAUNCH_CHECK();
-    if (values) {
-        if (!sse || !cnt) return JABBA_EINVAL;
-        JB_LAUNCH(k_recon_sse, dim3(waves_grid(n_series)), dim3(256), 0, st, out_off, series_off, n_series,
-                           values, out, sse, cnt);
-        JB_LAUNCH_CHECK();
-    }
     return JABBA_OK;
 }
 
@@ -409,7 +408,8 @@ extern "C" int jabba_reconstruct_pieces(const int32_t *len, const double *inc, c
     if (rc || n_series == 0) return rc;
     if (!t0 || !out) return JABBA_EINVAL;
     JB_LAUNCH(k_recon, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off, out_off, n_series,
-              t0, out, (int64_t *)nullptr);
+              t0, out, (int64_t *)nullptr, series_off, (const double *)nullptr, (double *)nullptr,
+              (int64_t *)nullptr);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
