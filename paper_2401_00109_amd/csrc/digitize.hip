@@ -321,14 +321,17 @@ struct Active {
     }
 };
 
+// Branch-free: both tests are always evaluated (pure comparisons, so the
+// result equals the short-circuit form), which lets several candidates'
+// FP64 chains overlap.
 __device__ __forceinline__ bool covers(double kq, double xq, double yq, double kp, double xp, double yp, double alpha,
                                        double a2) {
-    if (!(kq - kp <= alpha)) return false;
+    const bool in_window = kq - kp <= alpha;
     const double dx = xq - xp;
     const double dy = yq - yp;
     const double dd = dx * dx;
     const double ee = dy * dy;
-    return (dd + ee) <= a2;
+    return in_window & ((dd + ee) <= a2);
 }
 
 // Runs the greedy over positions [from, to) with the active list A as the
@@ -397,9 +400,13 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                             gy[u] = L->y[e];
                             gp[u] = L->p[e];
                         }
+                        bool hit[kGroup];
+#pragma unroll
+                        for (int u = 0; u < kGroup; ++u)
+                            hit[u] = (i + u < A.tail) & covers(kq, xq, yq, gk[u], gx[u], gy[u], alpha, a2);
 #pragma unroll
                         for (int u = 0; u < kGroup; ++u) {
-                            if (open && i + u < A.tail && covers(kq, xq, yq, gk[u], gx[u], gy[u], alpha, a2)) {
+                            if (open && hit[u]) {
                                 owner = gp[u];
                                 open = false;
                             }
