@@ -156,30 +156,58 @@ __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ 
     if (threadIdx.x == 0) ctl[kCtlFinal] = active & 1;
 }
 
+// Exclusive scan over the NT threads of a block (one value per thread).
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wave) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) s_wave[w] = x;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < w; ++q) add += s_wave[q];
+    __syncthreads();
+    return x - v + add;
+}
+
+// A pass over one tile of kTileN pairs with kSweepThreads threads: threads
+// below 256 own one digit each (histogram, look-back, bucket bases).
+constexpr int kSweepThreads = 512;
+constexpr int kSweepRounds = kTileN / kSweepThreads;
+
 template <int Tag>
-__global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
-                                                       uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
-                                                       const int64_t *n_dev, int64_t n_max, int shift, int32_t *ctl,
-                                                       int pass, const uint32_t *__restrict__ gbase,
-                                                       const unsigned long long *__restrict__ kmin,
-                                                       uint64_t *__restrict__ status, int32_t *__restrict__ tile_ctr) {
+__global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
+                                                            uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
+                                                            const int64_t *n_dev, int64_t n_max, int shift,
+                                                            int32_t *ctl, int pass, const uint32_t *__restrict__ gbase,
+                                                            const unsigned long long *__restrict__ kmin,
+                                                            uint64_t *__restrict__ status,
+                                                            int32_t *__restrict__ tile_ctr) {
     if (ctl[kCtlSkip + pass]) return;
-    constexpr int kWaves = kThreads / kWave;
-    constexpr int kPerWave = kTileN / kWaves;  // contiguous quarter of the tile per wavefront
+    constexpr int kWaves = kSweepThreads / kWave;
+    constexpr int kPerWave = kTileN / kWaves;  // contiguous slice of the tile per wavefront
     __shared__ uint64_t s_key[kTileN];
     __shared__ uint32_t s_val[kTileN];
     __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_lo[256];          // local start per digit
-    __shared__ uint32_t s_go[256];          // destination start per digit
+    __shared__ uint32_t s_lo[256];            // local start per digit
+    __shared__ uint32_t s_go[256];            // destination start per digit
     __shared__ uint32_t s_wrun[kWaves][256];  // per-wave count, then per-wave offset, per digit
     __shared__ uint32_t s_wave[kWaves];
     __shared__ int64_t s_tile;
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const int lane = tid & (kWave - 1);
+    const bool digit_owner = tid < 256;
     if (tid == 0) s_tile = atomicAdd(&tile_ctr[pass], 1);
-    s_hist[tid] = 0;
-    for (int q = 0; q < kWaves; ++q) s_wrun[q][tid] = 0;
+    if (digit_owner) {
+        s_hist[tid] = 0;
+        for (int q = 0; q < kWaves; ++q) s_wrun[q][tid] = 0;
+    }
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t n = live(n_dev, n_max);
@@ -196,31 +224,32 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
 
     // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
     // (wave, round, lane) order is index order; all loads in flight at once
-    uint64_t kr[kRounds];
-    uint32_t vr[kRounds];
+    uint64_t kr[kSweepRounds];
+    uint32_t vr[kSweepRounds];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < kSweepRounds; ++r) {
         const int li = w * kPerWave + r * kWave + lane;
         kr[r] = li < m ? ks[base + li] : 0ull;
         vr[r] = li < m ? vs[base + li] : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r)
+    for (int r = 0; r < kSweepRounds; ++r)
         if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[digit(kr[r])], 1u);
     __syncthreads();
-    const uint32_t cnt = s_hist[tid];
+    const uint32_t cnt = digit_owner ? s_hist[tid] : 0u;
 
     // publish this tile's counts early, so later tiles' look-backs find them
     const uint64_t tag = (uint64_t)(pass + 1) << 56;
-    __hip_atomic_store(&status[tile * 256 + tid], tag | (tile == 0 ? kFlagPre : kFlagAgg) | cnt, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    if (digit_owner)
+        __hip_atomic_store(&status[tile * 256 + tid], tag | (tile == 0 ? kFlagPre : kFlagAgg) | cnt,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     // wave-local ranking in index order: peers with the same digit by eight
     // ballots, a running count per digit in this wave's LDS row
-    uint32_t wpos[kRounds];
+    uint32_t wpos[kSweepRounds];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < kSweepRounds; ++r) {
         const bool ok = w * kPerWave + r * kWave + lane < m;
         const uint32_t dg = digit(kr[r]);
         uint64_t peers = __ballot(ok);
@@ -240,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
     // kWindow earlier tiles are read together; they are consumed newest
     // first until a prefix is found, waiting only on words not yet published.
     uint64_t excl = 0;
-    if (tile > 0) {
+    if (digit_owner && tile > 0) {
         constexpr int kWindow = 8;
         const uint64_t ready_tag = (uint64_t)(pass + 1);
         int64_t t = tile - 1;
@@ -275,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();  // every wave's counts are final
-    {
+    if (digit_owner) {
         uint32_t acc = 0;
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) {
@@ -284,11 +313,14 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
             acc += c;
         }
     }
-    s_lo[tid] = block_excl_scan_256(cnt, s_wave);
-    s_go[tid] = gbase[pass * 256 + tid] + (uint32_t)excl;
+    const uint32_t lo = block_excl_scan<kSweepThreads>(cnt, s_wave);
+    if (digit_owner) {
+        s_lo[tid] = lo;
+        s_go[tid] = gbase[pass * 256 + tid] + (uint32_t)excl;
+    }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < kSweepRounds; ++r) {
         if (w * kPerWave + r * kWave + lane < m) {
             const uint32_t dg = digit(kr[r]);
             const uint32_t lp = s_lo[dg] + s_wrun[w][dg] + wpos[r];
@@ -299,8 +331,8 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(uint64_t *__restrict__ k0
     __syncthreads();
     // leave in digit order: consecutive slots of one digit are consecutive destinations
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const int j = r * kThreads + tid;
+    for (int r = 0; r < kSweepRounds; ++r) {
+        const int j = r * kSweepThreads + tid;
         if (j < m) {
             const uint64_t key = s_key[j];
             const uint32_t dg = digit(key);
@@ -364,7 +396,7 @@ int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, 
     JB_LAUNCH_CHECK();
     for (int pass = 0; pass < 8; ++pass) {
         JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups", main_sort ? k_onesweep<0> : k_onesweep<1>,
-                        dim3((unsigned)tiles), dim3(kThreads), 0, st, b.keys[0], b.keys[1], b.vals[0], b.vals[1],
+                        dim3((unsigned)tiles), dim3(kSweepThreads), 0, st, b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                         n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.kmin, b.status, b.tile_ctr);
         JB_LAUNCH_CHECK();
     }
