@@ -254,6 +254,19 @@ def main() -> int:
                  "identical_outputs": bool(same)}
         log(f"compress: plain {ms_plain:.3f} ms ({w.n_series} launches) vs batched {ms_batched:.3f} ms")
 
+    # ---------------------------------------------------------------- digitization quality (not in the step)
+    step_sym()
+    ev0.record()
+    q = sz.quality()
+    ev1.record()
+    torch.cuda.synchronize()
+    qt = q["totals"].cpu().tolist()
+    quality = {"sse": qt[0], "max_var_len": qt[1], "max_var_inc": qt[2], "alpha_sq": w.alpha ** 2,
+               "sse_bound_two_stage": 4 * w.alpha ** 2 * (N - k), "quality_ms": round(ev0.elapsed_time(ev1), 3)}
+    log(f"quality: SSE {qt[0]:.6e} (two-stage bound {quality['sse_bound_two_stage']:.3e}), "
+        f"max Var_len {qt[1]:.3e}, max Var_inc {qt[2]:.3e} (alpha^2 {w.alpha ** 2:.3e}), "
+        f"{quality['quality_ms']} ms")
+
     # ---------------------------------------------------------------- pmc calibration copy
     if args.pmc_calibrate:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -296,6 +309,7 @@ def main() -> int:
         "batched_vs_plain": plain,
         "cpu_baseline": cpu,
         "reconstruction_mse": rec.mse(),
+        "digitization_quality": quality,
         "source_hash": source_hash(),
     }
     print(json.dumps(line), flush=True)

@@ -208,6 +208,30 @@ int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_piece
  */
 int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream, int64_t *stats);
 
+/*
+ * Quality of the digitization the workspace holds (Sec. 3.2: the vector
+ * quantization objective, Eq. sse, and the per-cluster variances, Eq. Var).
+ * Call after jabba_digitize with the same len, inc, n_pieces, max_pieces,
+ * alpha, B, dictionary and workspace, on the same stream, before the
+ * workspace is used again (this call overwrites parts of it that the
+ * digitization no longer needs).  With x = scl*(len/sigma_len) and
+ * y = inc/sigma_inc, the scaled coordinates the aggregation uses, and the
+ * symbol's scaled center (cx, cy):
+ *   var_len[c] = mean over the members of c of (x - cx_c)^2,
+ *   var_inc[c] = mean over the members of c of (y - cy_c)^2,
+ *   totals[0] = SSE, the sum over all pieces of (x - cx)^2 + (y - cy)^2,
+ *   totals[1] = max_c var_len[c], totals[2] = max_c var_inc[c].
+ * var_len, var_inc: device, dict->capacity entries (symbols >= capacity are
+ * skipped); totals: device, 3 entries.  Each squared deviation is one rounded
+ * binary64 value; they are summed per Stage I group in position order and
+ * per symbol over its groups, the same fixed order as the centers, and the
+ * SSE adds the per-symbol sums in a fixed order, so the results are
+ * deterministic.
+ */
+int jabba_digitize_quality(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                           double alpha, int32_t B, const jabba_dict *dict, double *var_len, double *var_inc,
+                           double *totals, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Workspace bytes for jabba_encode with a dictionary of this capacity. */
 int jabba_encode_workspace(int64_t capacity, size_t *bytes);
 
@@ -223,6 +247,38 @@ int jabba_encode_workspace(int64_t capacity, size_t *bytes);
  */
 int jabba_encode(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
                  const jabba_dict *dict, int32_t *symbols, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Workspace bytes for jabba_kmeans with at most max_pieces pieces and a
+ * dictionary of this capacity.
+ */
+int jabba_kmeans_workspace(int64_t max_pieces, int64_t capacity, size_t *bytes);
+
+/*
+ * k-means digitization with a given number of symbols (Sec. 3.2: Lloyd's
+ * algorithm for the vector quantization objective; the symbol count is the
+ * parameter C of Alg. 1).  Pieces are scaled as jabba_digitize scales them,
+ * x = scl*(len/sigma_len), y = inc/sigma_inc, with
+ *   dict->params[0..2] = sigma_len, sigma_inc, scl (device; e.g. as written
+ *   by a previous jabba_digitize), *dict->k = the number of centers k
+ *   (device, 1..capacity), dict->cx/cy = the k initial scaled centers.
+ * Each iteration assigns every piece to its nearest center exactly as
+ * jabba_encode does (rounded distances, ties to the lowest symbol), stops
+ * when no assignment changed, and otherwise moves every center to the mean of
+ * its members: center_len = exact integer sum of len / count, center_inc =
+ * the members' inc added one by one in canonical piece order / count,
+ * cx = scl*(center_len/sigma_len), cy = center_inc/sigma_inc; a center with
+ * no member keeps its position (count 0).  At most max_iter assignments.
+ * Outputs: symbols (device, max_pieces), the dictionary's cx, cy,
+ * center_len, center_inc, count (the means of the final assignment), and
+ * *iterations (device int64, assignments made).  center_len/center_inc of a
+ * center that never had a member are 0.  Synchronises `stream` once per
+ * iteration for the convergence check.  Ownership: all buffers belong to the
+ * caller; the workspace is reused between calls.
+ */
+int jabba_kmeans(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces, int32_t max_iter,
+                 const jabba_dict *dict, int32_t *symbols, int64_t *iterations, void *workspace,
+                 size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Inverse symbolization (Sec. 3.3).                                          */

@@ -720,3 +720,137 @@ int jo_encode(const int32_t *len, const double *inc, int64_t N, double sigma_len
     }
     return JO_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Quality of a digitization (Sec. 3.2: the VQ objective, Eq. sse, and the  */
+/* per-cluster variances, Eq. Var).  Pieces are scaled as the aggregation   */
+/* scales them, x_i = scl*(len_i/sigma_len), y_i = inc_i/sigma_inc, and     */
+/* compared with their symbol's scaled center (cx, cy), which is the mean   */
+/* of the members; so for symbol c with members S_c                         */
+/*   var_len[c] = (1/|S_c|) sum_{i in S_c} (x_i - cx_c)^2,                  */
+/*   var_inc[c] = (1/|S_c|) sum_{i in S_c} (y_i - cy_c)^2,                  */
+/*   SSE        = sum_c sum_{i in S_c} ((x_i - cx_c)^2 + (y_i - cy_c)^2).   */
+/* Each squared deviation is one rounded binary64 value; every sum is the   */
+/* exact sum of those values, rounded once (non-overlapping partials).      */
+/* count[c] = |S_c|.  A symbol outside [0, k) is an error.                  */
+/* ------------------------------------------------------------------------ */
+int jo_quality(const int32_t *len, const double *inc, const int32_t *symbols, int64_t N, double sigma_len,
+               double sigma_inc, double scl, const double *cx, const double *cy, int64_t k, double *var_len,
+               double *var_inc, int64_t *count, double *sse)
+{
+    if (N < 0 || k < 0) return JO_EINVAL;
+    for (int64_t i = 0; i < N; i++)
+        if (symbols[i] < 0 || symbols[i] >= k) return JO_EINVAL;
+    int rc = JO_ENOMEM;
+    int64_t *start = calloc((size_t)(k + 1), sizeof(int64_t));
+    int64_t *order = malloc((size_t)(N + 1) * sizeof(int64_t));
+    double *dx2 = malloc((size_t)(N + 1) * sizeof(double));
+    double *dy2 = malloc((size_t)(N + 1) * sizeof(double));
+    double *both = malloc((size_t)(2 * N + 1) * sizeof(double));
+    if (!start || !order || !dx2 || !dy2 || !both) goto done;
+    /* members of each symbol, in canonical order (counting sort) */
+    for (int64_t i = 0; i < N; i++) start[symbols[i] + 1]++;
+    for (int64_t c = 0; c < k; c++) start[c + 1] += start[c];
+    {
+        int64_t *fill = calloc((size_t)(k + 1), sizeof(int64_t));
+        if (!fill) goto done;
+        for (int64_t i = 0; i < N; i++) {
+            const int64_t c = symbols[i];
+            order[start[c] + fill[c]++] = i;
+        }
+        free(fill);
+    }
+    for (int64_t c = 0; c < k; c++) {
+        const int64_t a = start[c], b = start[c + 1];
+        for (int64_t j = a; j < b; j++) {
+            const int64_t i = order[j];
+            const double x = scl * ((double)len[i] / sigma_len);
+            const double y = inc[i] / sigma_inc;
+            const double ex = x - cx[c];
+            const double ey = y - cy[c];
+            dx2[j] = ex * ex;
+            dy2[j] = ey * ey;
+            both[2 * j] = dx2[j];
+            both[2 * j + 1] = dy2[j];
+        }
+        count[c] = b - a;
+        var_len[c] = b > a ? jo_exact_sum(dx2 + a, b - a) / (double)(b - a) : 0.0;
+        var_inc[c] = b > a ? jo_exact_sum(dy2 + a, b - a) / (double)(b - a) : 0.0;
+    }
+    *sse = jo_exact_sum(both, 2 * N);
+    rc = JO_OK;
+done:
+    free(start);
+    free(order);
+    free(dx2);
+    free(dy2);
+    free(both);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-means digitization with a given number of symbols (Sec. 3.2: Lloyd's   */
+/* algorithm minimises the VQ objective; Alg. 1 takes the symbol count as   */
+/* its parameter C).  Pieces are scaled as in jo_digitize with the given    */
+/* sigma and scl; the k initial centers (cx, cy) are inputs.  Each iteration */
+/*   1. assigns every piece to its nearest center (ties to the lowest       */
+/*      index, as in jo_encode), and stops when no assignment changed;      */
+/*   2. moves every center to the mean of its members: center_len = exact   */
+/*      integer sum of len / count, center_inc = sum of inc in canonical    */
+/*      piece order, left to right, / count; a center with no member stays. */
+/* After max_iter assignments the last assignment and its means are        */
+/* returned.  Reading: the paper fixes neither the summation order nor the  */
+/* initialisation; both are stated here and in the design notes.            */
+/* ------------------------------------------------------------------------ */
+int jo_kmeans(const int32_t *len, const double *inc, int64_t N, double sigma_len, double sigma_inc, double scl,
+              int64_t k, int64_t max_iter, double *cx, double *cy, double *center_len, double *center_inc,
+              int64_t *count, int32_t *symbols, int64_t *iters_done)
+{
+    if (k < 1 || N < 0 || max_iter < 1) return JO_EINVAL;
+    int rc = JO_ENOMEM;
+    int64_t *slen = malloc((size_t)k * sizeof(int64_t));
+    double *sinc = malloc((size_t)k * sizeof(double));
+    int32_t *prev = malloc((size_t)(N + 1) * sizeof(int32_t));
+    if (!slen || !sinc || !prev) goto done;
+    for (int64_t c = 0; c < k; c++) {
+        center_len[c] = 0.0;
+        center_inc[c] = 0.0;
+        count[c] = 0;
+    }
+    int64_t it = 0;
+    for (; it < max_iter; it++) {
+        rc = jo_encode(len, inc, N, sigma_len, sigma_inc, scl, cx, cy, k, symbols);
+        if (rc != JO_OK) goto done;
+        if (it > 0) {
+            int64_t changed = 0;
+            for (int64_t i = 0; i < N; i++) changed += symbols[i] != prev[i];
+            if (changed == 0) break;
+        }
+        for (int64_t c = 0; c < k; c++) {
+            slen[c] = 0;
+            sinc[c] = 0.0;
+            count[c] = 0;
+        }
+        for (int64_t i = 0; i < N; i++) {
+            const int32_t c = symbols[i];
+            slen[c] += len[i];
+            sinc[c] = sinc[c] + inc[i];
+            count[c] += 1;
+            prev[i] = c;
+        }
+        for (int64_t c = 0; c < k; c++) {
+            if (count[c] == 0) continue;
+            center_len[c] = (double)slen[c] / (double)count[c];
+            center_inc[c] = sinc[c] / (double)count[c];
+            cx[c] = scl * (center_len[c] / sigma_len);
+            cy[c] = center_inc[c] / sigma_inc;
+        }
+    }
+    *iters_done = it < max_iter ? it + 1 : max_iter;
+    rc = JO_OK;
+done:
+    free(slen);
+    free(sinc);
+    free(prev);
+    return rc;
+}

@@ -35,6 +35,10 @@ __all__ = [
     "reconstruct",
     "reconstruct_pieces",
     "encode",
+    "quality",
+    "Quality",
+    "kmeans",
+    "KMeans",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -128,6 +132,12 @@ def lib():
             L.jo_encode.restype = C.c_int
             L.jo_encode.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_double, _f64p, _f64p,
                                     C.c_int64, _i32p]
+            L.jo_kmeans.restype = C.c_int
+            L.jo_kmeans.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int64,
+                                    C.c_int64, _f64p, _f64p, _f64p, _f64p, _i64p, _i32p, C.POINTER(C.c_int64)]
+            L.jo_quality.restype = C.c_int
+            L.jo_quality.argtypes = [_i32p, _f64p, _i32p, C.c_int64, C.c_double, C.c_double, C.c_double, _f64p,
+                                     _f64p, C.c_int64, _f64p, _f64p, _i64p, C.POINTER(C.c_double)]
             _lib = L
     return _lib
 
@@ -299,3 +309,48 @@ def encode(length, inc, sigma_len, sigma_inc, scl, cx, cy):
     _check(lib().jo_encode(ln, ic, ln.size, float(sigma_len), float(sigma_inc), float(scl), cx, cy, cx.size, sym),
            "encode")
     return sym[: ln.size].copy()
+
+
+@dataclass
+class Quality:
+    var_len: np.ndarray
+    var_inc: np.ndarray
+    count: np.ndarray
+    sse: float
+
+
+def quality(length, inc, symbols, sigma_len, sigma_inc, scl, cx, cy) -> Quality:
+    """Per-symbol variances and the total SSE in scaled space (see jo_quality)."""
+    ln, ic, sym, cx, cy = _i32(length), _f64(inc), _i32(symbols), _f64(cx), _f64(cy)
+    k = cx.size
+    vl, vi = np.zeros(max(k, 1)), np.zeros(max(k, 1))
+    cnt = np.zeros(max(k, 1), np.int64)
+    sse = C.c_double()
+    _check(lib().jo_quality(ln, ic, sym, ln.size, float(sigma_len), float(sigma_inc), float(scl), cx, cy, k, vl, vi,
+                            cnt, C.byref(sse)), "quality")
+    return Quality(vl[:k].copy(), vi[:k].copy(), cnt[:k].copy(), float(sse.value))
+
+
+@dataclass
+class KMeans:
+    symbols: np.ndarray
+    cx: np.ndarray
+    cy: np.ndarray
+    center_len: np.ndarray
+    center_inc: np.ndarray
+    count: np.ndarray
+    iterations: int
+
+
+def kmeans(length, inc, sigma_len, sigma_inc, scl, cx0, cy0, max_iter) -> KMeans:
+    """Lloyd iterations from the given scaled centers (see jo_kmeans)."""
+    ln, ic = _i32(length), _f64(inc)
+    cx, cy = _f64(cx0).copy(), _f64(cy0).copy()
+    k = cx.size
+    cl, ci = np.zeros(k), np.zeros(k)
+    cnt = np.zeros(k, np.int64)
+    sym = np.zeros(max(ln.size, 1), np.int32)
+    it = C.c_int64()
+    _check(lib().jo_kmeans(ln, ic, ln.size, float(sigma_len), float(sigma_inc), float(scl), k, int(max_iter), cx, cy,
+                           cl, ci, cnt, sym, C.byref(it)), "kmeans")
+    return KMeans(sym[: ln.size].copy(), cx, cy, cl, ci, cnt, int(it.value))

@@ -28,6 +28,7 @@ EXPORTS = [
     "jabba_reconstruct_size", "jabba_reconstruct", "jabba_reconstruct_pieces", "jabba_workspace_status",
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
+    "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans",
 ]
 
 
@@ -98,6 +99,9 @@ def lib() -> C.CDLL:
             L.jabba_plan_destroy.argtypes = [P]
             L.jabba_fp64_selftest.argtypes = [P, P, P, P, I64, P]
             L.jabba_digitize_stats.argtypes = [P, I64, I32, P, C.POINTER(I64)]
+            L.jabba_digitize_quality.argtypes = [P, P, P, I64, D, I32, C.POINTER(Dict), P, P, P, P, SZ, P]
+            L.jabba_kmeans_workspace.argtypes = [I64, I64, C.POINTER(SZ)]
+            L.jabba_kmeans.argtypes = [P, P, P, I64, I32, C.POINTER(Dict), P, P, P, SZ, P]
             L.jabba_timing_enable.argtypes = [C.c_int]
             L.jabba_timing_get.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(I64)]
             L.jabba_timing_names.argtypes = [C.c_char_p, SZ]

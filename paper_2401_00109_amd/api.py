@@ -18,7 +18,7 @@ from . import _lib as L
 __all__ = [
     "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "reconstruct",
     "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
-    "timing_enable", "timing_report", "digitize_stats",
+    "timing_enable", "timing_report", "digitize_stats", "digitize_quality", "kmeans",
 ]
 
 
@@ -242,6 +242,48 @@ def digitize(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, ma
     return symbols, dictionary, workspace
 
 
+def digitize_quality(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, alpha: float,
+                     B: int, dictionary: Dictionary, workspace: torch.Tensor, stream=None) -> dict:
+    """Per-symbol variances and the SSE of the digitization in `workspace` (see jabba_digitize_quality).
+
+    Returns device tensors var_len, var_inc (dictionary capacity entries) and totals = [SSE, max var_len,
+    max var_inc]; enqueued on the stream, no synchronisation."""
+    dev = length.device
+    cap = dictionary.capacity
+    var_len = torch.zeros(max(cap, 1), dtype=torch.float64, device=dev)
+    var_inc = torch.zeros(max(cap, 1), dtype=torch.float64, device=dev)
+    totals = torch.zeros(3, dtype=torch.float64, device=dev)
+    d = dictionary.struct()
+    rc = L.lib().jabba_digitize_quality(_p(length), _p(inc), _p(n_pieces), int(max_pieces), float(alpha), int(B),
+                                        C.byref(d), _p(var_len), _p(var_inc), _p(totals), _p(workspace),
+                                        workspace.numel(), _stream(stream))
+    L.check(rc, "jabba_digitize_quality")
+    return {"var_len": var_len, "var_inc": var_inc, "totals": totals}
+
+
+def kmeans(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, dictionary: Dictionary,
+           max_iter: int = 100, symbols: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+           stream=None):
+    """Lloyd iterations from the dictionary's initial centers (see jabba_kmeans).
+
+    The dictionary's params (sigma_len, sigma_inc, scl), k and cx/cy are the inputs; its centers and counts
+    are overwritten with the result.  Returns (symbols, iterations tensor)."""
+    dev = length.device
+    if symbols is None:
+        symbols = torch.empty(max(max_pieces, 1), dtype=torch.int32, device=dev)
+    if workspace is None:
+        n = C.c_size_t()
+        L.check(L.lib().jabba_kmeans_workspace(int(max_pieces), int(dictionary.capacity), C.byref(n)),
+                "jabba_kmeans_workspace")
+        workspace = _ws(n.value, dev)
+    iters = torch.zeros(1, dtype=torch.int64, device=dev)
+    d = dictionary.struct()
+    rc = L.lib().jabba_kmeans(_p(length), _p(inc), _p(n_pieces), int(max_pieces), int(max_iter), C.byref(d),
+                              _p(symbols), _p(iters), _p(workspace), workspace.numel(), _stream(stream))
+    L.check(rc, "jabba_kmeans")
+    return symbols, iters
+
+
 def encode_workspace_bytes(capacity: int) -> int:
     n = C.c_size_t()
     L.check(L.lib().jabba_encode_workspace(int(capacity), C.byref(n)), "encode_workspace")
@@ -402,6 +444,12 @@ class Symbolizer:
 
     def stats(self) -> dict:
         return digitize_stats(self.dws, self.max_pieces, self.B)
+
+    def quality(self, stream=None) -> dict:
+        """Variances and SSE of the last digitize (call before the next run)."""
+        p = self.pieces
+        return digitize_quality(p.len, p.inc, p.n_pieces, self.max_pieces, self.alpha, self.B, self.dictionary,
+                                self.dws, stream=stream)
 
 
 class Reconstructor:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(BUILD, "libjabba.so")
-SOURCES = ["abi.hip", "scan.hip", "compress.hip", "sort.hip", "digitize.hip", "encode.hip", "reconstruct.hip",
+SOURCES = ["abi.hip", "scan.hip", "compress.hip", "sort.hip", "digitize.hip", "encode.hip", "reconstruct.hip", "kmeans.hip",
            "plan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",

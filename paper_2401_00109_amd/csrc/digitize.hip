@@ -791,6 +791,88 @@ __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, c
     }
 }
 
+// ------------------------------------------------------------ quality
+//
+// Squared deviation of every sorted piece from its symbol's scaled center.
+__global__ void k_q_values(const DigState *ds, const double *__restrict__ sx, const double *__restrict__ sy,
+                           const int32_t *__restrict__ lab, const uint32_t *__restrict__ sidx,
+                           const int32_t *__restrict__ glab, const uint32_t *__restrict__ gsym, jabba_dict dict,
+                           double *__restrict__ qx, double *__restrict__ qy) {
+    const int64_t n = ds->n;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = sidx[lab[p]];
+        const int64_t c = gsym[glab[g]];
+        double ex2 = 0.0, ey2 = 0.0;
+        if (c < dict.capacity) {
+            const double ex = sx[p] - dict.cx[c];
+            const double ey = sy[p] - dict.cy[c];
+            ex2 = ex * ex;
+            ey2 = ey * ey;
+        }
+        qx[p] = ex2;
+        qy[p] = ey2;
+    }
+}
+
+// per symbol: the mean squared deviations, and their sum for the SSE
+__global__ void k_q_symbols(const int64_t *__restrict__ g_count, const uint32_t *__restrict__ gflag,
+                            const uint32_t *__restrict__ gsym, const double *__restrict__ sum_x,
+                            const double *__restrict__ sum_y, jabba_dict dict, double *__restrict__ var_len,
+                            double *__restrict__ var_inc, double *__restrict__ per_symbol) {
+    const int64_t G = *g_count;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+        if (!gflag[g]) continue;
+        const int64_t c = gsym[g];
+        if (c >= dict.capacity) continue;
+        const double cnt = (double)dict.count[c];
+        var_len[c] = sum_x[g] / cnt;
+        var_inc[c] = sum_y[g] / cnt;
+        per_symbol[c] = sum_x[g] + sum_y[g];
+    }
+}
+
+// SSE = sum over symbols (each thread adds its strided symbols in order, then
+// a fixed tree over the threads), and the largest variances
+__global__ __launch_bounds__(1024) void k_q_totals(const int64_t *__restrict__ kp, int64_t capacity,
+                                                   const double *__restrict__ per_symbol,
+                                                   const double *__restrict__ var_len,
+                                                   const double *__restrict__ var_inc, double *__restrict__ totals) {
+    __shared__ double s_sum[1024 / kWave], s_ml[1024 / kWave], s_mi[1024 / kWave];
+    int64_t k = *kp;
+    k = k < 0 ? 0 : (k > capacity ? capacity : k);
+    double acc = 0.0, ml = 0.0, mi = 0.0;
+    for (int64_t c = threadIdx.x; c < k; c += blockDim.x) {
+        acc = acc + per_symbol[c];
+        ml = var_len[c] > ml ? var_len[c] : ml;
+        mi = var_inc[c] > mi ? var_inc[c] : mi;
+    }
+    acc = wave_tree_sum(acc);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double yl = __shfl_xor(ml, o), yi = __shfl_xor(mi, o);
+        ml = yl > ml ? yl : ml;
+        mi = yi > mi ? yi : mi;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        s_sum[w] = acc;
+        s_ml[w] = ml;
+        s_mi[w] = mi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0, a = 0.0, b = 0.0;
+        for (int q = 0; q < (int)(blockDim.x / kWave); ++q) {
+            t = t + s_sum[q];
+            a = s_ml[q] > a ? s_ml[q] : a;
+            b = s_mi[q] > b ? s_mi[q] : b;
+        }
+        totals[0] = t;
+        totals[1] = a;
+        totals[2] = b;
+    }
+}
+
 struct DigWs {
     DigState *ds;
     double *tree[2];
@@ -1056,5 +1138,56 @@ extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, i
     int64_t ng = 0;
     JB_HIP(hipMemcpy(&ng, w.n_groups, sizeof(int64_t), hipMemcpyDeviceToHost));
     stats[4] = ng;
+    return JABBA_OK;
+}
+
+// Quality of the digitization held by the workspace: the squared deviations
+// are summed per Stage I group and then per symbol by the same kernels and in
+// the same order as the centers.  Scratch: arrays the digitization no longer
+// needs (piece records, Stage II column copies, the final group sums).
+extern "C" int jabba_digitize_quality(const int32_t *len, const double *inc, const int64_t *n_pieces,
+                                      int64_t max_pieces, double alpha, int32_t B, const jabba_dict *dict,
+                                      double *var_len, double *var_inc, double *totals, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+    if (max_pieces < 0 || B < 1 || !n_pieces || !dict || !var_len || !var_inc || !totals) return JABBA_EINVAL;
+    if (!(alpha >= 0.0) || !(alpha <= 1.0e150)) return JABBA_EINVAL;
+    if (max_pieces >= ((int64_t)1 << 31) - 1) return JABBA_EOVERFLOW;
+    if (max_pieces > 0 && (!len || !inc)) return JABBA_EINVAL;
+    if (dict->capacity < 1 || !dict->k || !dict->cx || !dict->cy || !dict->count) return JABBA_EINVAL;
+    const DigWs w0 = carve_digitize(nullptr, max_pieces, B);
+    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    const DigWs w = carve_digitize(workspace, max_pieces, B);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = max_pieces > 0 ? max_pieces : 1;
+    const int64_t nblk = nblk_of(N, B);
+    const int64_t *n_live = &w.ds->n;
+    double *qx = reinterpret_cast<double *>(w.rec);  // 2N doubles of dead piece records
+    double *qy = qx + N;
+    JB_LAUNCH(k_q_values, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.sx, w.sy, w.lab, w.sidx, w.glab, w.gsym,
+              *dict, qx, qy);
+    JB_LAUNCH_CHECK();
+    double *q[2] = {qx, qy};
+    double *stage1[2] = {w.ck, w.cx};   // per Stage I group
+    double *stage2[2] = {w.cy, w.oinc}; // per symbol (indexed by its global start)
+    for (int a = 0; a < 2; ++a) {
+        JB_LAUNCH(k_block_sums, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, st, w.cuts, nblk, w.sidx, w.lab,
+                  w.slen, q[a], w.ocnt, w.olen, stage1[a]);
+        JB_LAUNCH_CHECK();
+        JB_LAUNCH((k_group_sums<true>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, n_live,
+                  w.spos, w.sblk, w.cuts, w.sidx, w.flag, w.sk, w.lab, w.slen, (const int64_t *)nullptr,
+                  (const int64_t *)nullptr, q[a], alpha, w.ocnt, w.olen, stage1[a]);
+        JB_LAUNCH_CHECK();
+        JB_LAUNCH((k_group_sums<false>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, w.g_count,
+                  (const int32_t *)nullptr, (const int32_t *)nullptr, (const int64_t *)nullptr,
+                  (const uint32_t *)nullptr, w.gflag, w.gk, w.glab, (const int32_t *)nullptr, w.gcnt, w.glen,
+                  stage1[a], alpha, w.ocnt, w.olen, stage2[a]);
+        JB_LAUNCH_CHECK();
+    }
+    double *per_symbol = w.gy;
+    JB_LAUNCH(k_q_symbols, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, stage2[0], stage2[1],
+              *dict, var_len, var_inc, per_symbol);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_q_totals, dim3(1), dim3(1024), 0, st, dict->k, dict->capacity, per_symbol, var_len, var_inc, totals);
+    JB_LAUNCH_CHECK();
     return JABBA_OK;
 }

@@ -66,3 +66,11 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_every_export_has_a_ctypes_signature():
+    # an entry point without argtypes would fail on its first float argument
+    from paper_2401_00109_amd import _lib
+    L = _lib.lib()
+    for name in _lib.EXPORTS:
+        assert getattr(L, name).argtypes is not None, f"{name} has no ctypes signature"

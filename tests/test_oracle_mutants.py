@@ -13,7 +13,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "jabba_oracle.c")
-PINS = ["tests/test_oracle_compress.py", "tests/test_oracle_digitize.py", "tests/test_oracle_reconstruct.py"]
+PINS = ["tests/test_oracle_compress.py", "tests/test_oracle_digitize.py", "tests/test_oracle_reconstruct.py",
+        "tests/test_oracle_quality.py", "tests/test_oracle_kmeans.py"]
 
 MUTANTS = {
     "square_dropped": ("acc = acc + r * r;", "acc = acc + r;"),
@@ -36,6 +37,13 @@ MUTANTS = {
     "fill_index": ("out[o + pos + q] = V + slope * (double)q;", "out[o + pos + q] = V + slope * (double)(q + 1);"),
     "encode_ties_high": ("if (best < 0 || d2 < bd) {", "if (best < 0 || d2 <= bd) {"),
     "exact_sum_lossy": ("double lo = y - (hi - x);", "double lo = 0.0;"),
+    "quality_var_divisor": ("var_len[c] = b > a ? jo_exact_sum(dx2 + a, b - a) / (double)(b - a) : 0.0;",
+                            "var_len[c] = b > a ? jo_exact_sum(dx2 + a, b - a) / (double)(b - a + 1) : 0.0;"),
+    "quality_dy_from_x": ("const double ey = y - cy[c];", "const double ey = x - cy[c];"),
+    "quality_sse_half": ("*sse = jo_exact_sum(both, 2 * N);", "*sse = jo_exact_sum(both, N);"),
+    "kmeans_inc_mean_divisor": ("center_inc[c] = sinc[c] / (double)count[c];",
+                                "center_inc[c] = sinc[c] / (double)(count[c] + 1);"),
+    "kmeans_stops_early": ("if (changed == 0) break;", "if (changed < 3) break;"),
     "round_floor": ("return (int64_t)((v + ((i128)1 << (FIX_SHIFT - 1))) >> FIX_SHIFT);",
                     "return (int64_t)(v >> FIX_SHIFT);"),
 }
