@@ -83,3 +83,20 @@ def test_sse_never_increases():
         if prev is not None:
             assert sse <= prev * (1 + 1e-12)
         prev = sse
+
+
+def test_lloyd_from_the_aggregation_codebook_lowers_its_sse():
+    # Lloyd seeded with the greedy aggregation's centers ends at or below the
+    # aggregation's SSE (Sec. 5: aggregation is a suboptimal k-means solution),
+    # which itself stays under alpha^2 (N - k).
+    rng = np.random.default_rng(5)
+    ln = rng.integers(1, 6, 3000).astype(np.int32)
+    inc = rng.normal(0, 1, 3000)
+    alpha = 0.2
+    d = O.digitize(ln, inc, alpha, 1.0, 1 << 30)
+    agg = O.quality(ln, inc, d.symbols, d.sigma_len, d.sigma_inc, 1.0, d.cx, d.cy).sse
+    assert agg <= alpha ** 2 * (ln.size - d.k) * (1 + 1e-12)
+    r = O.kmeans(ln, inc, d.sigma_len, d.sigma_inc, 1.0, d.cx.copy(), d.cy.copy(), 50)
+    km = O.quality(ln, inc, r.symbols, d.sigma_len, d.sigma_inc, 1.0, r.cx, r.cy).sse
+    assert km <= agg * (1 + 1e-12)
+    assert km < agg  # the aggregation's assignment is not nearest-center here, so Lloyd moves it
