@@ -303,6 +303,81 @@ int jo_scaling(const int32_t *len, const double *inc, int64_t N, double scl, dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* PCA sort key (Sec. 5 allows the projection on a principal axis in place of  */
+/* the norm).  The points are the scaled pieces p_i = (x_i, y_i).  Their       */
+/* population covariance follows from the scaling itself:                    */
+/*   var(x)    = scl^2 * var_len / sigma_len^2  = scl^2 (0 when var_len = 0), */
+/*   var(y)    = var_inc / sigma_inc^2          = 1     (0 when var_inc = 0), */
+/*   cov(x, y) = scl * cov(len, inc) / (sigma_len * sigma_inc),               */
+/* where cov(len, inc) = T((len_i - S1/N) * (inc_i - T(inc)/N)) / N with the   */
+/* pairwise tree T of the increment deviation (and 0 when either variance is  */
+/* 0).  For the symmetric matrix [[a, c], [c, b]] the larger eigenvalue is     */
+/* l = (a + b)/2 + r, r = sqrt(((a - b)/2)^2 + c^2); an eigenvector is         */
+/* (l - b, c) = (h + r, c) and also (c, l - a) = (c, r - h), h = (a - b)/2;    */
+/* the form whose first entry has no cancellation is taken (h >= 0: the       */
+/* first), normalised, and signed so that its first nonzero entry is          */
+/* positive.  c = 0 gives the coordinate axis of the larger variance (x on a  */
+/* tie).  The key is u_x*x_i + u_y*y_i, with -0 taken as +0.  Only +, -, *, / */
+/* and sqrt appear, all correctly rounded.                                    */
+/* ------------------------------------------------------------------------ */
+int jo_pca_axis(const int32_t *len, const double *inc, int64_t N, double scl, double *axis)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (N > 0) {
+        int64_t S1 = 0, S2 = 0;
+        for (int64_t i = 0; i < N; i++) {
+            S1 += len[i];
+            S2 += (int64_t)len[i] * (int64_t)len[i];
+        }
+        double mean_len = (double)S1 / (double)N;
+        double var_len = (double)S2 / (double)N - mean_len * mean_len;
+        if (var_len < 0.0) var_len = 0.0;
+        double sl = sqrt(var_len);
+        double mean_inc = jo_tree_sum(inc, N) / (double)N;
+        double *t = (double *)malloc((size_t)N * sizeof(double));
+        if (!t) return JO_ENOMEM;
+        for (int64_t i = 0; i < N; i++) {
+            double d = inc[i] - mean_inc;
+            t[i] = d * d;
+        }
+        double var_inc = jo_tree_sum(t, N) / (double)N;
+        for (int64_t i = 0; i < N; i++) t[i] = ((double)len[i] - mean_len) * (inc[i] - mean_inc);
+        double cov = jo_tree_sum(t, N) / (double)N;
+        free(t);
+        double si = sqrt(var_inc);
+        if (var_len > 0.0 && sl > 0.0) a = scl * scl;
+        if (var_inc > 0.0 && si > 0.0) b = 1.0;
+        if (a > 0.0 && b > 0.0) c = scl * ((cov / sl) / si);
+    }
+    double ux, uy;
+    if (c == 0.0) {
+        ux = a >= b ? 1.0 : 0.0;
+        uy = a >= b ? 0.0 : 1.0;
+    } else {
+        double h = 0.5 * (a - b);
+        double r = sqrt(h * h + c * c);
+        double vx, vy;
+        if (h >= 0.0) {
+            vx = h + r;
+            vy = c;
+        } else {
+            vx = c;
+            vy = r - h;
+        }
+        if (vx < 0.0) {
+            vx = -vx;
+            vy = -vy;
+        }
+        double n = sqrt(vx * vx + vy * vy);
+        ux = vx / n;
+        uy = vy / n;
+    }
+    axis[0] = ux;
+    axis[1] = uy;
+    return JO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sort (Sec. 5: one global sorting index).  Ascending key; equal keys keep   */
 /* the canonical piece order.                                                 */
 /* ------------------------------------------------------------------------ */
@@ -385,7 +460,8 @@ void jo_aggregate_sorted(const double *sx, const double *sy, const double *skey,
 /*
  * Phase III: two-stage digitization (Sec. 5) and the dictionary.
  *
- *  1. scaling and key (jo_scaling), global sort (jo_sort_order);
+ *  1. scaling and key (jo_scaling; with key_kind 1 the projection on the
+ *     principal axis of jo_pca_axis), global sort (jo_sort_order);
  *  2. Stage I: aggregation inside every block of B sorted pieces;
  *  3. Stage II: the same aggregation over the collected starting points,
  *     which are a subsequence of the sorted order and so already sorted;
@@ -412,11 +488,13 @@ void jo_aggregate_sorted(const double *sx, const double *sy, const double *skey,
  *   center_len/inc, cx, cy, count: capacity entries
  * Returns k (number of symbols) or a negative status.
  */
-int64_t jo_digitize(const int32_t *len, const double *inc, int64_t N, double alpha, double scl, int64_t B,
-                    int64_t capacity, int32_t *symbols, int64_t *perm_out, int64_t *local_start_out,
-                    int64_t *n_starts_out, int64_t *gmap_out, double *sigma, double *center_len,
-                    double *center_inc, double *cx, double *cy, int64_t *count, int64_t *n_blocks_out)
+int64_t jo_digitize_key(const int32_t *len, const double *inc, int64_t N, double alpha, double scl, int64_t B,
+                        int key_kind, double *axis_out, int64_t capacity, int32_t *symbols, int64_t *perm_out,
+                        int64_t *local_start_out, int64_t *n_starts_out, int64_t *gmap_out, double *sigma,
+                        double *center_len, double *center_inc, double *cx, double *cy, int64_t *count,
+                        int64_t *n_blocks_out)
 {
+    if (key_kind != 0 && key_kind != 1) return JO_EINVAL;
     if (!(alpha >= 0.0) || !(scl >= 0.0) || B < 1 || N < 0) return JO_EINVAL;
     for (int64_t i = 0; i < N; i++)
         if (!isfinite(inc[i]) || len[i] < 1) return JO_EINVAL;
@@ -444,6 +522,19 @@ int64_t jo_digitize(const int32_t *len, const double *inc, int64_t N, double alp
 
     rc = jo_scaling(len, inc, N, scl, &sl, &si, x, y, key);
     if (rc != JO_OK) goto done;
+    if (key_kind == 1) {
+        double u[2];
+        rc = jo_pca_axis(len, inc, N, scl, u);
+        if (rc != JO_OK) goto done;
+        for (int64_t i = 0; i < N; i++) {
+            double kv = u[0] * x[i] + u[1] * y[i];
+            key[i] = kv == 0.0 ? 0.0 : kv;
+        }
+        if (axis_out) {
+            axis_out[0] = u[0];
+            axis_out[1] = u[1];
+        }
+    }
     if (sigma) {
         sigma[0] = sl;
         sigma[1] = si;
@@ -538,6 +629,16 @@ done:
     free(glab);
     free(gsym);
     return rc == JO_OK ? k : rc;
+}
+
+/* The two-stage digitization with the norm key. */
+int64_t jo_digitize(const int32_t *len, const double *inc, int64_t N, double alpha, double scl, int64_t B,
+                    int64_t capacity, int32_t *symbols, int64_t *perm_out, int64_t *local_start_out,
+                    int64_t *n_starts_out, int64_t *gmap_out, double *sigma, double *center_len,
+                    double *center_inc, double *cx, double *cy, int64_t *count, int64_t *n_blocks_out)
+{
+    return jo_digitize_key(len, inc, N, alpha, scl, B, 0, NULL, capacity, symbols, perm_out, local_start_out,
+                           n_starts_out, gmap_out, sigma, center_len, center_inc, cx, cy, count, n_blocks_out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -24,6 +24,7 @@ __all__ = [
     "count_domains",
     "domains",
     "compress",
+    "pca_axis",
     "tree_sum",
     "exact_sum",
     "scaling",
@@ -122,6 +123,12 @@ def lib():
             L.jo_digitize.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64,
                                       _i32p, _i64n, _i64n, C.POINTER(C.c_int64), _i64n, _f64n, _f64n, _f64n,
                                       _f64n, _f64n, _i64n, C.POINTER(C.c_int64)]
+            L.jo_digitize_key.restype = C.c_int64
+            L.jo_digitize_key.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int,
+                                          _f64n, C.c_int64, _i32p, _i64n, _i64n, C.POINTER(C.c_int64), _i64n,
+                                          _f64n, _f64n, _f64n, _f64n, _f64n, _i64n, C.POINTER(C.c_int64)]
+            L.jo_pca_axis.restype = C.c_int
+            L.jo_pca_axis.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, _f64p]
             L.jo_reconstruct_size.restype = C.c_int
             L.jo_reconstruct_size.argtypes = [_i32p, _i64p, _i64p, C.c_int64, _f64p, C.c_int64, _i64p]
             L.jo_reconstruct.restype = C.c_int
@@ -247,10 +254,25 @@ class Digitized:
     n_starts: int
     gmap: np.ndarray
     n_blocks: int
+    axis: np.ndarray | None = None  # unit principal axis (key="pca" only)
 
 
-def digitize(length, inc, alpha: float, scl: float = 1.0, B: int = 4096, capacity: int | None = None) -> Digitized:
-    """Two-stage digitization and dictionary (see jo_digitize)."""
+KEYS = {"norm": 0, "pca": 1}
+
+
+def pca_axis(length, inc, scl: float = 1.0) -> np.ndarray:
+    """Unit principal axis of the scaled pieces (see jo_pca_axis)."""
+    ln, ic = _i32(length), _f64(inc)
+    u = np.zeros(2)
+    _check(lib().jo_pca_axis(ln, ic, ln.size, float(scl), u), "pca_axis")
+    return u
+
+
+def digitize(length, inc, alpha: float, scl: float = 1.0, B: int = 4096, capacity: int | None = None,
+             key: str = "norm") -> Digitized:
+    """Two-stage digitization and dictionary (see jo_digitize_key); key "norm" or "pca"."""
+    if key not in KEYS:
+        raise ValueError(f"key must be one of {sorted(KEYS)}")
     ln, ic = _i32(length), _f64(inc)
     n = ln.size
     cap = n if capacity is None else int(capacity)
@@ -263,12 +285,13 @@ def digitize(length, inc, alpha: float, scl: float = 1.0, B: int = 4096, capacit
     cnt = np.zeros(max(cap, 1), np.int64)
     g = C.c_int64()
     nb = C.c_int64()
-    k = _check(lib().jo_digitize(ln, ic, n, float(alpha), float(scl), int(B), cap, sym, perm, lst, C.byref(g),
-                                 gmap, sig, cl, ci, cx, cy, cnt, C.byref(nb)), "digitize")
+    axis = np.zeros(2)
+    k = _check(lib().jo_digitize_key(ln, ic, n, float(alpha), float(scl), int(B), KEYS[key], axis, cap, sym, perm,
+                                     lst, C.byref(g), gmap, sig, cl, ci, cx, cy, cnt, C.byref(nb)), "digitize")
     G = g.value
     return Digitized(sym[:n].copy(), int(k), float(sig[0]), float(sig[1]), float(scl), float(alpha),
                      cl[:k].copy(), ci[:k].copy(), cx[:k].copy(), cy[:k].copy(), cnt[:k].copy(), perm[:n].copy(),
-                     lst[:n].copy(), int(G), gmap[:G].copy(), int(nb.value))
+                     lst[:n].copy(), int(G), gmap[:G].copy(), int(nb.value), axis if key == "pca" else None)
 
 
 def reconstruct(symbols, piece_off, series_off, t0, center_len, center_inc, orig=None):

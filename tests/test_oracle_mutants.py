@@ -14,7 +14,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "jabba_oracle.c")
 PINS = ["tests/test_oracle_compress.py", "tests/test_oracle_digitize.py", "tests/test_oracle_reconstruct.py",
-        "tests/test_oracle_quality.py", "tests/test_oracle_kmeans.py"]
+        "tests/test_oracle_quality.py", "tests/test_oracle_kmeans.py", "tests/test_oracle_pca.py"]
 
 MUTANTS = {
     "square_dropped": ("acc = acc + r * r;", "acc = acc + r;"),
@@ -44,6 +44,12 @@ MUTANTS = {
     "kmeans_inc_mean_divisor": ("center_inc[c] = sinc[c] / (double)count[c];",
                                 "center_inc[c] = sinc[c] / (double)(count[c] + 1);"),
     "kmeans_stops_early": ("if (changed == 0) break;", "if (changed < 3) break;"),
+    "pca_cov_uncentered": ("t[i] = ((double)len[i] - mean_len) * (inc[i] - mean_inc);",
+                           "t[i] = (double)len[i] * inc[i];"),
+    "pca_cov_sign": ("c = scl * ((cov / sl) / si);", "c = -scl * ((cov / sl) / si);"),
+    "pca_var_x_unsquared": ("a = scl * scl;", "a = scl;"),
+    "pca_minor_axis": ("vx = h + r;", "vx = h - r;"),
+    "pca_key_transposed": ("double kv = u[0] * x[i] + u[1] * y[i];", "double kv = u[1] * x[i] + u[0] * y[i];"),
     "round_floor": ("return (int64_t)((v + ((i128)1 << (FIX_SHIFT - 1))) >> FIX_SHIFT);",
                     "return (int64_t)(v >> FIX_SHIFT);"),
 }
