@@ -199,6 +199,45 @@ int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_piece
                    void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * jabba_digitize with a PCA projection as the sort key (Sec. 5 names the norm
+ * or a PCA projection as the scalar the pieces are sorted by).  Step 1 also
+ * forms the population covariance of the scaled points:
+ *   var(x) = scl^2 (0 when var_len = 0), var(y) = 1 (0 when var_inc = 0),
+ *   cov(x, y) = scl*((cov(len, inc)/sigma_len)/sigma_inc), 0 unless both
+ *   variances are positive, with cov(len, inc) = T((len - S1/N)*(inc - T(inc)/N))/N
+ *   and T the pairwise sum of step 1;
+ * the key is u_x*x + u_y*y (no fused multiply-add; -0 taken as +0), u the unit
+ * eigenvector of the larger eigenvalue of that 2x2 matrix in closed form
+ * ((h + r, c) if h >= 0 else (c, r - h), h = (var(x) - var(y))/2,
+ * r = sqrt(h^2 + cov^2), normalised), signed so its first nonzero entry is
+ * positive; a zero covariance gives (1, 0) if var(x) >= var(y), else (0, 1).
+ * Keys may be negative.  Steps 2-7 are those of jabba_digitize; the pruning
+ * in steps 4-5 stays sound because a projection on a unit vector never
+ * exceeds the distance.
+ *  axis: device, 2 doubles, out (may be NULL): u_x, u_y.
+ * Arguments, workspace size, errors and device status as jabba_digitize.
+ */
+int jabba_digitize_pca(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                       double alpha, double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols,
+                       const jabba_dict *dict, double *axis, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Separate digitization tolerances for length and increment (Sec. 3.2,
+ * alpha_len and alpha_inc of Eq. Var1).  A piece joins a start when
+ *   ((x - x_s)/alpha_len)^2 + ((y - y_s)/alpha_inc)^2 <= 1,
+ * which is the aggregation's test when alpha_len = alpha_inc = alpha.  The
+ * same test is the aggregation's disc test of radius alpha_inc after x is
+ * multiplied by alpha_inc/alpha_len, so this host function only returns the
+ * jabba_digitize (or jabba_digitize_pca) arguments that run it:
+ *   *alpha = alpha_inc,  *scl = scl_in*(alpha_inc/alpha_len)
+ * and the test evaluated is that rescaled disc test.  With one block every
+ * symbol then has Var_len <= alpha_len^2 (x in units of scl_in*len/sigma_len)
+ * and Var_inc <= alpha_inc^2, hence Eq. Var1.  alpha_len, alpha_inc > 0 and
+ * scl_in >= 0, all finite, else JABBA_EINVAL.  No device work.
+ */
+int jabba_axis_tolerances(double alpha_len, double alpha_inc, double scl_in, double *alpha, double *scl);
+
+/*
  * Counters of the last jabba_digitize that used `workspace` (same max_pieces
  * and B): stats[0] = N pieces, stats[1] = G Stage I starting points,
  * stats[2] = k symbols, stats[3] = radix passes that moved data (digits that

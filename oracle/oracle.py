@@ -25,6 +25,7 @@ __all__ = [
     "domains",
     "compress",
     "pca_axis",
+    "axis_tolerances",
     "tree_sum",
     "exact_sum",
     "scaling",
@@ -266,6 +267,18 @@ def pca_axis(length, inc, scl: float = 1.0) -> np.ndarray:
     u = np.zeros(2)
     _check(lib().jo_pca_axis(ln, ic, ln.size, float(scl), u), "pca_axis")
     return u
+
+
+def axis_tolerances(alpha_len: float, alpha_inc: float, scl: float = 1.0) -> tuple[float, float]:
+    """Separate length and increment tolerances (Sec. 3.2, Eq. Var1).
+
+    A piece joins a start when ((x - x_s)/alpha_len)^2 + ((y - y_s)/alpha_inc)^2 <= 1, which is the
+    aggregation's test for alpha_len = alpha_inc.  Multiplying x by alpha_inc/alpha_len turns it into the
+    disc test of radius alpha_inc, so the variant is the aggregation run with (alpha, scl) returned here."""
+    alpha_len, alpha_inc, scl = float(alpha_len), float(alpha_inc), float(scl)
+    if not (alpha_len > 0 and alpha_inc > 0 and scl >= 0) or not all(map(np.isfinite, (alpha_len, alpha_inc, scl))):
+        raise ValueError("alpha_len, alpha_inc > 0 and scl >= 0, finite")
+    return alpha_inc, scl * (alpha_inc / alpha_len)
 
 
 def digitize(length, inc, alpha: float, scl: float = 1.0, B: int = 4096, capacity: int | None = None,

@@ -28,7 +28,8 @@ EXPORTS = [
     "jabba_reconstruct_size", "jabba_reconstruct", "jabba_reconstruct_pieces", "jabba_workspace_status",
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
-    "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans",
+    "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans", "jabba_digitize_pca",
+    "jabba_axis_tolerances",
 ]
 
 
@@ -87,6 +88,9 @@ def lib() -> C.CDLL:
             L.jabba_compress_plain.argtypes = [P, P, P, I64, I32, D, I32, P, P, P, P, P, SZ, P]
             L.jabba_digitize_workspace.argtypes = [I64, I32, C.POINTER(SZ)]
             L.jabba_digitize.argtypes = [P, P, P, I64, D, D, I32, C.POINTER(Tuning), P, C.POINTER(Dict), P, SZ, P]
+            L.jabba_digitize_pca.argtypes = [P, P, P, I64, D, D, I32, C.POINTER(Tuning), P, C.POINTER(Dict), P, P,
+                                             SZ, P]
+            L.jabba_axis_tolerances.argtypes = [D, D, D, C.POINTER(D), C.POINTER(D)]
             L.jabba_encode_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_encode.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
             L.jabba_reconstruct_workspace.argtypes = [I64, C.POINTER(SZ)]

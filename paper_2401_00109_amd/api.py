@@ -18,7 +18,7 @@ from . import _lib as L
 __all__ = [
     "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "reconstruct",
     "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
-    "timing_enable", "timing_report", "digitize_stats", "digitize_quality", "kmeans",
+    "timing_enable", "timing_report", "digitize_stats", "digitize_quality", "kmeans", "axis_tolerances",
 ]
 
 
@@ -225,8 +225,14 @@ def compress_plain(values: torch.Tensor, series_off: torch.Tensor, series_off_ho
 def digitize(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, alpha: float,
              scl: float = 1.0, B: int = 4096, capacity: int | None = None, tuning: dict | None = None,
              symbols: torch.Tensor | None = None, dictionary: Dictionary | None = None,
-             workspace: torch.Tensor | None = None, stream=None):
-    """Phase III of Alg. 1 (two-stage digitization).  Returns (symbols, Dictionary, workspace)."""
+             workspace: torch.Tensor | None = None, stream=None, key: str = "norm", axis: torch.Tensor | None = None):
+    """Phase III of Alg. 1 (two-stage digitization).  Returns (symbols, Dictionary, workspace).
+
+    key "norm" sorts by sqrt(x^2 + y^2) (jabba_digitize); "pca" by the projection on the principal axis
+    (jabba_digitize_pca), which is written to `axis` (2 float64 on the device, allocated when None) and kept as
+    ``dictionary.axis``."""
+    if key not in ("norm", "pca"):
+        raise ValueError(f"key must be 'norm' or 'pca', not {key!r}")
     dev = length.device
     if symbols is None:
         symbols = torch.empty(max(max_pieces, 1), dtype=torch.int32, device=dev)
@@ -236,10 +242,28 @@ def digitize(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, ma
         workspace = _ws(digitize_workspace_bytes(max_pieces, B), dev)
     d = dictionary.struct()
     t = tuning_struct(tuning)
+    if key == "pca":
+        if axis is None:
+            axis = torch.zeros(2, dtype=torch.float64, device=dev)
+        rc = L.lib().jabba_digitize_pca(_p(length), _p(inc), _p(n_pieces), int(max_pieces), float(alpha), float(scl),
+                                        int(B), _tref(t), _p(symbols), C.byref(d), _p(axis), _p(workspace),
+                                        workspace.numel(), _stream(stream))
+        L.check(rc, "jabba_digitize_pca")
+        dictionary.axis = axis
+        return symbols, dictionary, workspace
     rc = L.lib().jabba_digitize(_p(length), _p(inc), _p(n_pieces), int(max_pieces), float(alpha), float(scl), int(B),
                                 _tref(t), _p(symbols), C.byref(d), _p(workspace), workspace.numel(), _stream(stream))
     L.check(rc, "jabba_digitize")
     return symbols, dictionary, workspace
+
+
+def axis_tolerances(alpha_len: float, alpha_inc: float, scl: float = 1.0) -> tuple[float, float]:
+    """(alpha, scl) for digitize that run the aggregation with separate length and increment tolerances
+    (jabba_axis_tolerances, Sec. 3.2 Eq. Var1)."""
+    a, s_ = C.c_double(), C.c_double()
+    L.check(L.lib().jabba_axis_tolerances(float(alpha_len), float(alpha_inc), float(scl), C.byref(a), C.byref(s_)),
+            "jabba_axis_tolerances")
+    return a.value, s_.value
 
 
 def digitize_quality(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int, alpha: float,

@@ -34,6 +34,9 @@ struct DigState {
     double mean_inc;
     double sigma_len;
     double sigma_inc;
+    double var_len;   // before a zero deviation is replaced by 1
+    double var_inc;
+    double axis[2];   // unit principal axis (PCA key)
     int64_t n;  // live piece count (clamped)
     int64_t sort_passes;  // radix passes of the main sort that moved data
 };
@@ -62,8 +65,9 @@ __device__ __forceinline__ double block_tree_1024(double a0, double a1, double a
     return r;
 }
 
-// level 0: leaves are inc (pass 1) or (inc - mean)^2 (pass 2); pass 1 also
-// accumulates the exact integer sums of len and len^2.
+// level 0: leaves are inc (pass 1), (inc - mean_inc)^2 (pass 2) or
+// (len - mean_len)*(inc - mean_inc) (pass 3, the PCA key's covariance); pass 1
+// also accumulates the exact integer sums of len and len^2.
 template <int Pass>
 __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ len, const double *__restrict__ inc,
                                                     DigState *ds, double *__restrict__ out,
@@ -73,7 +77,8 @@ __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ 
     const int64_t base = (int64_t)blockIdx.x * kTreeLeaves + 4 * threadIdx.x;
     double a[4];
     unsigned long long s1 = 0, s2 = 0;
-    const double mean = Pass == 2 ? ds->mean_inc : 0.0;
+    const double mean = Pass >= 2 ? ds->mean_inc : 0.0;
+    const double mean_len = Pass == 3 && n > 0 ? (double)(int64_t)ds->lsum[0] / (double)n : 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t idx = base + i;
@@ -83,6 +88,9 @@ __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ 
             if (Pass == 2) {
                 const double d = v - mean;
                 v = d * d;
+            } else if (Pass == 3) {
+                const double dl = (double)len[idx] - mean_len;
+                v = dl * (v - mean);
             } else {
                 const unsigned long long l = (unsigned long long)len[idx];
                 s1 += l;
@@ -174,6 +182,11 @@ __global__ void k_sigma(DigState *ds, const double *total2, double scl, double a
         si = __dsqrt_rn(var_inc);
         if (!(sl > 0.0)) sl = 1.0;
         if (!(si > 0.0)) si = 1.0;
+        ds->var_len = var_len;
+        ds->var_inc = var_inc;
+    } else {
+        ds->var_len = 0.0;
+        ds->var_inc = 0.0;
     }
     ds->sigma_len = sl;
     ds->sigma_inc = si;
@@ -185,6 +198,69 @@ __global__ void k_sigma(DigState *ds, const double *total2, double scl, double a
     }
 }
 
+// Principal axis of the scaled pieces (Sec. 5, PCA projection as the sort
+// key).  By construction var(x) = scl^2 and var(y) = 1 (0 when the raw
+// variance is 0) and cov(x, y) = scl*cov(len, inc)/(sigma_len*sigma_inc), with
+// cov(len, inc) the pass-3 pairwise sum over N.  The eigenvector of the larger
+// eigenvalue of [[a, c], [c, b]] is (h + r, c) or (c, r - h), h = (a - b)/2,
+// r = sqrt(h^2 + c^2), whichever has no cancellation in its first entry;
+// normalised and signed so its first nonzero entry is positive.  Only
+// correctly rounded operations, in a fixed order.
+__global__ void k_pca_axis(DigState *ds, const double *total3, double scl, double *axis_out) {
+    if (threadIdx.x != 0) return;
+    const int64_t n = ds->n;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (n > 0) {
+        const double cov = (*total3) / (double)n;
+        if (ds->var_len > 0.0) a = scl * scl;
+        if (ds->var_inc > 0.0) b = 1.0;
+        if (a > 0.0 && b > 0.0) c = scl * ((cov / ds->sigma_len) / ds->sigma_inc);
+    }
+    double ux, uy;
+    if (c == 0.0) {
+        ux = a >= b ? 1.0 : 0.0;
+        uy = a >= b ? 0.0 : 1.0;
+    } else {
+        const double h = 0.5 * (a - b);
+        const double r = __dsqrt_rn(h * h + c * c);
+        double vx, vy;
+        if (h >= 0.0) {
+            vx = h + r;
+            vy = c;
+        } else {
+            vx = c;
+            vy = r - h;
+        }
+        if (vx < 0.0) {
+            vx = -vx;
+            vy = -vy;
+        }
+        const double nn = __dsqrt_rn(vx * vx + vy * vy);
+        ux = vx / nn;
+        uy = vy / nn;
+    }
+    ds->axis[0] = ux;
+    ds->axis[1] = uy;
+    if (axis_out) {
+        axis_out[0] = ux;
+        axis_out[1] = uy;
+    }
+}
+
+// Sort keys as unsigned integers in the order of the doubles: -0 is taken as
+// +0, a non-negative key gets its sign bit set, a negative one is inverted.
+__device__ __forceinline__ uint64_t key_bits(double k) {
+    const uint64_t b = (uint64_t)__double_as_longlong(k == 0.0 ? 0.0 : k);
+    return (b >> 63) ? ~b : (b | ((uint64_t)1 << 63));
+}
+__device__ __forceinline__ double key_of_bits(uint64_t b) {
+    return __longlong_as_double((long long)((b >> 63) ? (b & ~((uint64_t)1 << 63)) : ~b));
+}
+
+// key kinds
+constexpr int kKeyNorm = 0;
+constexpr int kKeyPca = 1;
+
 // One piece as a 16-byte record, so that reading it in sorted (random)
 // order touches one cache line instead of one per array.
 struct __align__(16) PieceRec {
@@ -193,15 +269,25 @@ struct __align__(16) PieceRec {
     int32_t pad;
 };
 
+template <int Key>
 __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict__ inc, const DigState *ds, double scl,
                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, PieceRec *__restrict__ rec) {
     const int64_t n = ds->n;
     const double sl = ds->sigma_len, si = ds->sigma_inc;
+    const double ux = Key == kKeyPca ? ds->axis[0] : 0.0, uy = Key == kKeyPca ? ds->axis[1] : 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t l = len[i];
         const double ic = inc[i];
         const Scaled s = scale_piece(l, ic, scl, sl, si);
-        keys[i] = (uint64_t)__double_as_longlong(piece_key(s));
+        double k;
+        if (Key == kKeyPca) {
+            const double px = ux * s.x;
+            const double py = uy * s.y;
+            k = px + py;
+        } else {
+            k = piece_key(s);
+        }
+        keys[i] = key_bits(k);
         vals[i] = (uint32_t)i;
         PieceRec r;
         r.inc = ic;
@@ -232,7 +318,7 @@ __global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds,
         const int32_t l = r.len;
         const double ic = r.inc;
         const Scaled s = scale_piece(l, ic, scl, sl, si);
-        sk[p] = __longlong_as_double((long long)ks[p]);
+        sk[p] = key_of_bits(ks[p]);
         sx[p] = s.x;
         sy[p] = s.y;
         slen[p] = l;
@@ -1005,9 +1091,12 @@ extern "C" int jabba_digitize_workspace(int64_t max_pieces, int32_t B, size_t *b
     return JABBA_OK;
 }
 
-extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
-                              double alpha, double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols,
-                              const jabba_dict *dict, void *workspace, size_t workspace_bytes, void *stream) {
+namespace jabba {
+namespace {
+
+int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces, double alpha,
+                  double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols, const jabba_dict *dict,
+                  int key_kind, double *axis_out, void *workspace, size_t workspace_bytes, void *stream) {
     if (max_pieces < 0 || B < 1 || !n_pieces || !dict) return JABBA_EINVAL;
     if (!(alpha >= 0.0) || !(alpha <= 1.0e150) || !(scl >= 0.0) || !(scl <= 1.0e150)) return JABBA_EINVAL;
     if (max_pieces >= ((int64_t)1 << 31) - 1) return JABBA_EOVERFLOW;
@@ -1046,11 +1135,25 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     if (rc) return rc;
     JB_LAUNCH(k_sigma, dim3(1), dim3(64), 0, st, w.ds, tot, scl, alpha, dict->params);
     JB_LAUNCH_CHECK();
+    if (key_kind == kKeyPca) {
+        // third pairwise-sum pass: covariance of len and inc, then the axis
+        JB_LAUNCH((k_sum_leaves<3>), dim3((unsigned)t0), dim3(256), 0, st, len, inc, w.ds, w.tree[0], w.lpart);
+        JB_LAUNCH_CHECK();
+        rc = tree_sum_levels(w, N, w.tree[0], st, &tot);
+        if (rc) return rc;
+        JB_LAUNCH(k_pca_axis, dim3(1), dim3(64), 0, st, w.ds, tot, scl, axis_out);
+        JB_LAUNCH_CHECK();
+    }
 
     // key and global sorting index
     rc = radix_sort_init(w.sb, st);
     if (rc) return rc;
-    JB_LAUNCH(k_key, dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl, w.sb.keys[0], w.sb.vals[0], w.rec);
+    if (key_kind == kKeyPca)
+        JB_LAUNCH_NAMED("k_key_pca", (k_key<kKeyPca>), dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl,
+                        w.sb.keys[0], w.sb.vals[0], w.rec);
+    else
+        JB_LAUNCH_NAMED("k_key", (k_key<kKeyNorm>), dim3(grid_for(N)), dim3(256), 0, st, len, inc, w.ds, scl,
+                        w.sb.keys[0], w.sb.vals[0], w.rec);
     JB_LAUNCH_CHECK();
     const int64_t *n_live = &w.ds->n;
     rc = radix_global_hist(w.sb, n_live, N, st);
@@ -1117,6 +1220,35 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
     JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, symbols);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
+}
+
+}  // namespace
+}  // namespace jabba
+
+extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                              double alpha, double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols,
+                              const jabba_dict *dict, void *workspace, size_t workspace_bytes, void *stream) {
+    return digitize_impl(len, inc, n_pieces, max_pieces, alpha, scl, B, tuning, symbols, dict, kKeyNorm, nullptr,
+                         workspace, workspace_bytes, stream);
+}
+
+extern "C" int jabba_axis_tolerances(double alpha_len, double alpha_inc, double scl_in, double *alpha,
+                                     double *scl) {
+    if (!alpha || !scl) return JABBA_EINVAL;
+    if (!(alpha_len > 0.0) || !(alpha_len <= 1.0e150) || !(alpha_inc > 0.0) || !(alpha_inc <= 1.0e150) ||
+        !(scl_in >= 0.0) || !(scl_in <= 1.0e150))
+        return JABBA_EINVAL;
+    *alpha = alpha_inc;
+    *scl = scl_in * (alpha_inc / alpha_len);
+    return JABBA_OK;
+}
+
+extern "C" int jabba_digitize_pca(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                                  double alpha, double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols,
+                                  const jabba_dict *dict, double *axis, void *workspace, size_t workspace_bytes,
+                                  void *stream) {
+    return digitize_impl(len, inc, n_pieces, max_pieces, alpha, scl, B, tuning, symbols, dict, kKeyPca, axis,
+                         workspace, workspace_bytes, stream);
 }
 
 extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream,

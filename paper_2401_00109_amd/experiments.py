@@ -15,6 +15,11 @@ pieces, pieces added by the partition boundaries, symbols, and for both
 digitizations the reconstruction MSE and the VQ objective (Eq. sse).
 
     python -m paper_2401_00109_amd.experiments --partitions 1,2,4,8,16,32,64
+
+The digitizer sweep (scl, separate tolerances, PCA key) runs on a compressed
+workload of the input recipe:
+
+    python -m paper_2401_00109_amd.experiments --sweep '[{"scl": 0}, {"scl": 1}, {"key": "pca"}]'
 """
 from __future__ import annotations
 
@@ -117,17 +122,66 @@ def noise_partitions(partitions, n: int = 100_000, tol: float = 0.01, alpha: flo
     return rows
 
 
+def digitizer_sweep(settings, workload_id: int = 2, scale: float = 1.0, seed: int = 0, B: int | None = None,
+                    device=None) -> list[dict]:
+    """The digitizer variants of Sec. 3.2 and Sec. 5 on one compressed workload.
+
+    Each setting is a dict with optional keys scl (length weight, Sec. 3.2: 0 clusters increments only, 1
+    weighs both alike), alpha, alpha_len / alpha_inc (separate tolerances, Eq. Var1; they replace alpha and
+    scale scl) and key ("norm" or "pca", Sec. 5).  The series are compressed once on the device; per setting
+    the device digitizes, reports k, the Stage I starting points, the VQ objective and largest per-symbol
+    variances in the digitizer's own scaled space (Eq. sse, Eq. Var), and the reconstruction MSE."""
+    from .inputs import make_workload
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    w = make_workload(workload_id, seed, scale)
+    v = torch.from_numpy(w.values).to(dev)
+    so = torch.from_numpy(w.series_off).to(dev)
+    t0 = torch.from_numpy(w.values[w.series_off[:-1]].copy()).to(dev)
+    B = w.B if B is None else int(B)
+    p = api.compress(v, so, w.D, w.tol, w.max_len)
+    torch.cuda.synchronize()
+    N = p.count()
+    rows = []
+    for st in settings:
+        scl = float(st.get("scl", w.scl))
+        alpha = float(st.get("alpha", w.alpha))
+        if "alpha_len" in st:
+            alpha, scl = api.axis_tolerances(st["alpha_len"], st["alpha_inc"], scl)
+        key = st.get("key", "norm")
+        sym, d, ws = api.digitize(p.len, p.inc, p.n_pieces, p.max_pieces, alpha, scl, B, key=key)
+        q = api.digitize_quality(p.len, p.inc, p.n_pieces, p.max_pieces, alpha, B, d, ws)
+        r = api.reconstruct(sym, p.piece_off, so, t0, d, values=v)
+        torch.cuda.synchronize()
+        stats = api.digitize_stats(ws, p.max_pieces, B)
+        tot = q["totals"].cpu().numpy()
+        row = dict(st)
+        row.update({"workload": workload_id, "pieces": N, "alpha_used": alpha, "scl_used": scl, "symbols": d.size(),
+                    "starts": stats["G"], "sse": float(tot[0]), "max_var_len": float(tot[1]),
+                    "max_var_inc": float(tot[2]),
+                    "mse": float(r["sse"].sum().item()) / max(int(r["cnt"].sum().item()), 1)})
+        if key == "pca":
+            row["axis"] = d.axis.cpu().numpy().tolist()
+        rows.append(row)
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--partitions", default="1,2,4,8,16,32,64,128")
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--kmeans-init", default="aggregation", choices=["aggregation", "spread"])
     ap.add_argument("--kmeans-iter", type=int, default=100)
+    ap.add_argument("--sweep", default="", help="digitizer settings as JSON list (runs the sweep instead)")
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--scale", type=float, default=1.0)
     a = ap.parse_args()
-    rows = noise_partitions([int(m) for m in a.partitions.split(",")], n=a.n, kmeans_iter=a.kmeans_iter,
-                            kmeans_init=a.kmeans_init)
+    if a.sweep:
+        rows = digitizer_sweep(json.loads(a.sweep), workload_id=a.workload, scale=a.scale)
+    else:
+        rows = noise_partitions([int(m) for m in a.partitions.split(",")], n=a.n, kmeans_iter=a.kmeans_iter,
+                                kmeans_init=a.kmeans_init)
     for r in rows:
-        print(json.dumps(r))
+        print(json.dumps(r), flush=True)
     return 0
 
 

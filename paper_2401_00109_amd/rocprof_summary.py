@@ -47,6 +47,8 @@ def timing_name(kernel: str) -> str:
         return "k_compress<W>"
     if base == "k_onesweep":
         return base + ("_groups" if targs == "<1>" else "")
+    if base == "k_key":
+        return base + ("_pca" if targs == "<1>" else "")
     return base + targs
 
 

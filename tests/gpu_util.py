@@ -42,7 +42,7 @@ def gpu_compress(values, series_off, D, tol, max_len=0, tuning=None, plain=False
     return ln, inc, po, st
 
 
-def gpu_digitize(ln, inc, alpha, scl=1.0, B=4096, capacity=None, tuning=None, max_pieces=None):
+def gpu_digitize(ln, inc, alpha, scl=1.0, B=4096, capacity=None, tuning=None, max_pieces=None, key="norm"):
     import paper_2401_00109_amd as J
     T = torch()
     n = int(np.asarray(ln).size)
@@ -53,10 +53,12 @@ def gpu_digitize(ln, inc, alpha, scl=1.0, B=4096, capacity=None, tuning=None, ma
         L[:n] = to_dev(np.asarray(ln, np.int32))
         I[:n] = to_dev(np.asarray(inc, np.float64))
     npc = T.tensor([n], dtype=T.int64, device=DEV)
-    sym, d, ws = J.digitize(L, I, npc, mp, alpha, scl, B, capacity=capacity, tuning=tuning)
+    sym, d, ws = J.digitize(L, I, npc, mp, alpha, scl, B, capacity=capacity, tuning=tuning, key=key)
     T.cuda.synchronize()
     st = J.workspace_status(ws)
     h = d.host()
+    if key == "pca":
+        h["axis"] = d.axis.cpu().numpy()
     h["stats"] = J.api.digitize_stats(ws, mp, B)
     return sym[:n].cpu().numpy(), h, st
 
