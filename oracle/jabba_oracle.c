@@ -458,6 +458,91 @@ void jo_aggregate_sorted(const double *sx, const double *sy, const double *skey,
 }
 
 /*
+ * Steps 2-4 of Phase III on points that are already in their final
+ * coordinates: global sort by key (ties by index), Stage I in every block,
+ * Stage II over the starting points, label propagation.  Returns k or
+ * JO_ENOMEM; the optional outputs are those of jo_digitize.
+ */
+static int64_t two_stage(const double *x, const double *y, const double *key, int64_t N, double alpha, int64_t B,
+                         int32_t *symbols, int64_t *perm_out, int64_t *local_start_out, int64_t *n_starts_out,
+                         int64_t *gmap_out, int64_t *n_blocks_out)
+{
+    int64_t k = 0, rc = JO_ENOMEM;
+    double *sx = malloc((size_t)(N + 1) * sizeof(double));
+    double *sy = malloc((size_t)(N + 1) * sizeof(double));
+    double *sk = malloc((size_t)(N + 1) * sizeof(double));
+    int64_t *perm = malloc((size_t)(N + 1) * sizeof(int64_t));
+    int64_t *lab = malloc((size_t)(N + 1) * sizeof(int64_t));
+    int64_t *bstart = malloc((size_t)(N + 2) * sizeof(int64_t));
+    int64_t *sidx = malloc((size_t)(N + 1) * sizeof(int64_t));
+    double *gx = calloc((size_t)(N + 1), sizeof(double));
+    double *gy = calloc((size_t)(N + 1), sizeof(double));
+    double *gk = calloc((size_t)(N + 1), sizeof(double));
+    int64_t *glab = malloc((size_t)(N + 1) * sizeof(int64_t));
+    int64_t *gsym = malloc((size_t)(N + 1) * sizeof(int64_t));
+    if (!sx || !sy || !sk || !perm || !lab || !bstart || !sidx || !gx || !gy || !gk || !glab || !gsym) goto done;
+
+    jo_sort_order(key, N, perm);
+    for (int64_t i = 0; i < N; i++) {
+        sx[i] = x[perm[i]];
+        sy[i] = y[perm[i]];
+        sk[i] = key[perm[i]];
+    }
+
+    /* Stage I */
+    int64_t M = jo_blocks(sk, N, B, bstart);
+    if (n_blocks_out) *n_blocks_out = M;
+    for (int64_t b = 0; b < M; b++) aggregate_range(sx, sy, sk, bstart[b], bstart[b + 1], alpha, lab);
+
+    /* starting points in sorted order */
+    int64_t G = 0;
+    for (int64_t i = 0; i < N; i++) {
+        if (lab[i] == i) {
+            sidx[i] = G;
+            gx[G] = sx[i];
+            gy[G] = sy[i];
+            gk[G] = sk[i];
+            G++;
+        } else
+            sidx[i] = -1;
+    }
+    if (n_starts_out) *n_starts_out = G;
+
+    /* Stage II */
+    aggregate_range(gx, gy, gk, 0, G, alpha, glab);
+    for (int64_t g = 0; g < G; g++) gsym[g] = (glab[g] == g) ? k++ : -1;
+    for (int64_t g = 0; g < G; g++) gsym[g] = gsym[glab[g]];
+    if (gmap_out)
+        for (int64_t g = 0; g < G; g++) gmap_out[g] = gsym[g];
+
+    /* label propagation */
+    for (int64_t i = 0; i < N; i++) {
+        int64_t sym = gsym[sidx[lab[i]]];
+        symbols[perm[i]] = (int32_t)sym;
+    }
+    if (perm_out)
+        for (int64_t i = 0; i < N; i++) perm_out[i] = perm[i];
+    if (local_start_out)
+        for (int64_t i = 0; i < N; i++) local_start_out[i] = lab[i];
+
+    rc = k;
+done:
+    free(sx);
+    free(sy);
+    free(sk);
+    free(perm);
+    free(lab);
+    free(bstart);
+    free(sidx);
+    free(gx);
+    free(gy);
+    free(gk);
+    free(glab);
+    free(gsym);
+    return rc;
+}
+
+/*
  * Phase III: two-stage digitization (Sec. 5) and the dictionary.
  *
  *  1. scaling and key (jo_scaling; with key_kind 1 the projection on the
@@ -504,21 +589,7 @@ int64_t jo_digitize_key(const int32_t *len, const double *inc, int64_t N, double
     double *x = malloc((size_t)(N + 1) * sizeof(double));
     double *y = malloc((size_t)(N + 1) * sizeof(double));
     double *key = malloc((size_t)(N + 1) * sizeof(double));
-    double *sx = malloc((size_t)(N + 1) * sizeof(double));
-    double *sy = malloc((size_t)(N + 1) * sizeof(double));
-    double *sk = malloc((size_t)(N + 1) * sizeof(double));
-    int64_t *perm = malloc((size_t)(N + 1) * sizeof(int64_t));
-    int64_t *lab = malloc((size_t)(N + 1) * sizeof(int64_t));
-    int64_t *bstart = malloc((size_t)(N + 2) * sizeof(int64_t));
-    int64_t *sidx = malloc((size_t)(N + 1) * sizeof(int64_t));
-    double *gx = malloc((size_t)(N + 1) * sizeof(double));
-    double *gy = malloc((size_t)(N + 1) * sizeof(double));
-    double *gk = malloc((size_t)(N + 1) * sizeof(double));
-    int64_t *glab = malloc((size_t)(N + 1) * sizeof(int64_t));
-    int64_t *gsym = malloc((size_t)(N + 1) * sizeof(int64_t));
-    if (!x || !y || !key || !sx || !sy || !sk || !perm || !lab || !bstart || !sidx || !gx || !gy || !gk ||
-        !glab || !gsym)
-        goto done;
+    if (!x || !y || !key) goto done;
 
     rc = jo_scaling(len, inc, N, scl, &sl, &si, x, y, key);
     if (rc != JO_OK) goto done;
@@ -539,48 +610,11 @@ int64_t jo_digitize_key(const int32_t *len, const double *inc, int64_t N, double
         sigma[0] = sl;
         sigma[1] = si;
     }
-    jo_sort_order(key, N, perm);
-    for (int64_t i = 0; i < N; i++) {
-        sx[i] = x[perm[i]];
-        sy[i] = y[perm[i]];
-        sk[i] = key[perm[i]];
+    k = two_stage(x, y, key, N, alpha, B, symbols, perm_out, local_start_out, n_starts_out, gmap_out, n_blocks_out);
+    if (k < 0) {
+        rc = (int)k;
+        goto done;
     }
-
-    /* Stage I */
-    int64_t M = jo_blocks(sk, N, B, bstart);
-    if (n_blocks_out) *n_blocks_out = M;
-    for (int64_t b = 0; b < M; b++) aggregate_range(sx, sy, sk, bstart[b], bstart[b + 1], alpha, lab);
-
-    /* starting points in sorted order */
-    int64_t G = 0;
-    for (int64_t i = 0; i < N; i++) {
-        if (lab[i] == i) {
-            sidx[i] = G;
-            gx[G] = sx[i];
-            gy[G] = sy[i];
-            gk[G] = sk[i];
-            G++;
-        } else
-            sidx[i] = -1;
-    }
-    if (n_starts_out) *n_starts_out = G;
-
-    /* Stage II */
-    aggregate_range(gx, gy, gk, 0, G, alpha, glab);
-    for (int64_t g = 0; g < G; g++) gsym[g] = (glab[g] == g) ? k++ : -1;
-    for (int64_t g = 0; g < G; g++) gsym[g] = gsym[glab[g]];
-    if (gmap_out)
-        for (int64_t g = 0; g < G; g++) gmap_out[g] = gsym[g];
-
-    /* label propagation */
-    for (int64_t i = 0; i < N; i++) {
-        int64_t sym = gsym[sidx[lab[i]]];
-        symbols[perm[i]] = (int32_t)sym;
-    }
-    if (perm_out)
-        for (int64_t i = 0; i < N; i++) perm_out[i] = perm[i];
-    if (local_start_out)
-        for (int64_t i = 0; i < N; i++) local_start_out[i] = lab[i];
 
     /* dictionary */
     rc = JO_OK;
@@ -616,19 +650,61 @@ done:
     free(x);
     free(y);
     free(key);
-    free(sx);
-    free(sy);
-    free(sk);
-    free(perm);
-    free(lab);
-    free(bstart);
-    free(sidx);
-    free(gx);
-    free(gy);
-    free(gk);
-    free(glab);
-    free(gsym);
     return rc == JO_OK ? k : rc;
+}
+
+/*
+ * Two-stage aggregation of 2-D points as given (Sec. 5; the Gaussian-blob
+ * experiment of Sec. 7.1 aggregates raw points and compares the two-stage
+ * result with the serial greedy aggregation, which is the case B >= N).
+ * key = sqrt(x*x + y*y); labels by steps 2-4 of Phase III.  Centers: the
+ * member count and the means of x and of y with the members added one by
+ * one in input order.  SSE (Eq. sse): the exact sum over the points of
+ * (x - cx)^2 + (y - cy)^2, each term rounded as written.
+ * Returns k, JO_ECAPACITY when k > capacity (labels and k still valid), or
+ * another negative status.
+ */
+int64_t jo_aggregate_points(const double *x, const double *y, int64_t N, double alpha, int64_t B, int64_t capacity,
+                            int32_t *labels, double *cx, double *cy, int64_t *count, double *sse, int64_t *n_starts_out,
+                            int64_t *n_blocks_out)
+{
+    if (!(alpha >= 0.0) || B < 1 || N < 0) return JO_EINVAL;
+    for (int64_t i = 0; i < N; i++)
+        if (!isfinite(x[i]) || !isfinite(y[i])) return JO_EINVAL;
+    double *key = malloc((size_t)(N + 1) * sizeof(double));
+    if (!key) return JO_ENOMEM;
+    for (int64_t i = 0; i < N; i++) key[i] = sqrt(x[i] * x[i] + y[i] * y[i]);
+    int64_t k = two_stage(x, y, key, N, alpha, B, labels, NULL, NULL, n_starts_out, NULL, n_blocks_out);
+    free(key);
+    if (k < 0) return k;
+    if (k > capacity) return JO_ECAPACITY;
+    for (int64_t c = 0; c < k; c++) {
+        cx[c] = 0.0;
+        cy[c] = 0.0;
+        count[c] = 0;
+    }
+    for (int64_t i = 0; i < N; i++) {
+        int64_t c = labels[i];
+        cx[c] = cx[c] + x[i];
+        cy[c] = cy[c] + y[i];
+        count[c] += 1;
+    }
+    for (int64_t c = 0; c < k; c++) {
+        cx[c] = cx[c] / (double)count[c];
+        cy[c] = cy[c] / (double)count[c];
+    }
+    if (sse) {
+        double *t = malloc((size_t)(N + 1) * sizeof(double));
+        if (!t) return JO_ENOMEM;
+        for (int64_t i = 0; i < N; i++) {
+            const double dx = x[i] - cx[labels[i]];
+            const double dy = y[i] - cy[labels[i]];
+            t[i] = dx * dx + dy * dy;
+        }
+        *sse = jo_exact_sum(t, N);
+        free(t);
+    }
+    return k;
 }
 
 /* The two-stage digitization with the norm key. */

@@ -26,6 +26,8 @@ __all__ = [
     "compress",
     "pca_axis",
     "axis_tolerances",
+    "aggregate_points",
+    "Aggregated",
     "tree_sum",
     "exact_sum",
     "scaling",
@@ -129,6 +131,10 @@ def lib():
                                           _f64n, C.c_int64, _i32p, _i64n, _i64n, C.POINTER(C.c_int64), _i64n,
                                           _f64n, _f64n, _f64n, _f64n, _f64n, _i64n, C.POINTER(C.c_int64)]
             L.jo_pca_axis.restype = C.c_int
+            L.jo_aggregate_points.restype = C.c_int64
+            L.jo_aggregate_points.argtypes = [_f64p, _f64p, C.c_int64, C.c_double, C.c_int64, C.c_int64, _i32p,
+                                              _f64p, _f64p, _i64p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int64)]
             L.jo_pca_axis.argtypes = [_i32p, _f64p, C.c_int64, C.c_double, _f64p]
             L.jo_reconstruct_size.restype = C.c_int
             L.jo_reconstruct_size.argtypes = [_i32p, _i64p, _i64p, C.c_int64, _f64p, C.c_int64, _i64p]
@@ -267,6 +273,32 @@ def pca_axis(length, inc, scl: float = 1.0) -> np.ndarray:
     u = np.zeros(2)
     _check(lib().jo_pca_axis(ln, ic, ln.size, float(scl), u), "pca_axis")
     return u
+
+
+@dataclass
+class Aggregated:
+    labels: np.ndarray
+    k: int
+    cx: np.ndarray
+    cy: np.ndarray
+    count: np.ndarray
+    sse: float
+    n_starts: int
+    n_blocks: int
+
+
+def aggregate_points(x, y, alpha: float, B: int = 1 << 62) -> Aggregated:
+    """Two-stage aggregation of raw 2-D points (see jo_aggregate_points); B >= N is the serial greedy."""
+    xs, ys = _f64(x), _f64(y)
+    n = xs.size
+    lab = np.zeros(max(n, 1), np.int32)
+    cx, cy = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+    cnt = np.zeros(max(n, 1), np.int64)
+    sse, g, nb = C.c_double(), C.c_int64(), C.c_int64()
+    k = _check(lib().jo_aggregate_points(xs, ys, n, float(alpha), int(B), max(n, 1), lab, cx, cy, cnt, C.byref(sse),
+                                         C.byref(g), C.byref(nb)), "aggregate_points")
+    return Aggregated(lab[:n].copy(), int(k), cx[:k].copy(), cy[:k].copy(), cnt[:k].copy(), float(sse.value),
+                      int(g.value), int(nb.value))
 
 
 def axis_tolerances(alpha_len: float, alpha_inc: float, scl: float = 1.0) -> tuple[float, float]:

@@ -14,7 +14,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "jabba_oracle.c")
 PINS = ["tests/test_oracle_compress.py", "tests/test_oracle_digitize.py", "tests/test_oracle_reconstruct.py",
-        "tests/test_oracle_quality.py", "tests/test_oracle_kmeans.py", "tests/test_oracle_pca.py"]
+        "tests/test_oracle_quality.py", "tests/test_oracle_kmeans.py", "tests/test_oracle_pca.py",
+        "tests/test_oracle_points.py"]
 
 MUTANTS = {
     "square_dropped": ("acc = acc + r * r;", "acc = acc + r;"),
@@ -50,6 +51,10 @@ MUTANTS = {
     "pca_var_x_unsquared": ("a = scl * scl;", "a = scl;"),
     "pca_minor_axis": ("vx = h + r;", "vx = h - r;"),
     "pca_key_transposed": ("double kv = u[0] * x[i] + u[1] * y[i];", "double kv = u[1] * x[i] + u[0] * y[i];"),
+    "points_cy_from_x": ("cy[c] = cy[c] + y[i];", "cy[c] = cy[c] + x[i];"),
+    "points_key_without_y": ("for (int64_t i = 0; i < N; i++) key[i] = sqrt(x[i] * x[i] + y[i] * y[i]);",
+                             "for (int64_t i = 0; i < N; i++) key[i] = fabs(x[i]);"),
+    "points_sse_dy_dropped": ("t[i] = dx * dx + dy * dy;", "t[i] = dx * dx;"),
     "round_floor": ("return (int64_t)((v + ((i128)1 << (FIX_SHIFT - 1))) >> FIX_SHIFT);",
                     "return (int64_t)(v >> FIX_SHIFT);"),
 }
