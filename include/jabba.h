@@ -192,7 +192,9 @@ int jabba_digitize_workspace(int64_t max_pieces, int32_t B, size_t *bytes);
  *  alpha >= 0, scl >= 0 finite; B >= 1 pieces per block (a method parameter:
  *  it changes results); symbols[max_pieces]: out.
  *  dict: out; dict->capacity symbols.  Device status JABBA_ECAPACITY when k >
- *  capacity (k is still written; only the first capacity centers are).
+ *  capacity (k is still written; only the first capacity centers are);
+ *  JABBA_ENONFINITE when an increment is NaN or infinite (results are then
+ *  unspecified).
  */
 int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces, double alpha,
                    double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols, const jabba_dict *dict,
@@ -220,6 +222,30 @@ int jabba_digitize(const int32_t *len, const double *inc, const int64_t *n_piece
 int jabba_digitize_pca(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
                        double alpha, double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols,
                        const jabba_dict *dict, double *axis, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Two-stage greedy aggregation of 2-D points as given, with no scaling
+ * (Sec. 5; the Gaussian-blob experiment of Sec. 7.1 runs the two-stage
+ * method on raw points and compares it with the serial greedy aggregation,
+ * which is B >= n).  key = sqrt(x*x + y*y); steps 2-6 of jabba_digitize
+ * (sort, blocks of B, Stage I, Stage II, label propagation) give labels
+ * numbered by sorted position of the global start.  Then per label: count,
+ * and the means of x and of y with the members added one by one in input
+ * order; and SSE (Eq. sse) = sum of (x - cx)^2 + (y - cy)^2 over the points,
+ * a pairwise tree in input order (within ~1e-15 relative of the exact sum).
+ *  x, y: n_points[0] points (device count, <= max_points), finite.
+ *  alpha >= 0; B >= 1 points per block.
+ *  labels[max_points]: out.  cx, cy, count: capacity entries, out.
+ *  k: device, 1 entry, out (written also when k > capacity; then device
+ *  status JABBA_ECAPACITY, centers beyond capacity and the SSE are not
+ *  written).  sse: device, 1 entry, out (may be NULL).
+ *  workspace: jabba_digitize_workspace(max_points, B) bytes.
+ * Non-finite points set device status JABBA_ENONFINITE.
+ */
+int jabba_aggregate_points(const double *x, const double *y, const int64_t *n_points, int64_t max_points,
+                           double alpha, int32_t B, int32_t *labels, int64_t capacity, double *cx, double *cy,
+                           int64_t *count, int64_t *k, double *sse, void *workspace, size_t workspace_bytes,
+                           void *stream);
 
 /*
  * Separate digitization tolerances for length and increment (Sec. 3.2,

@@ -29,7 +29,7 @@ EXPORTS = [
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
     "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans", "jabba_digitize_pca",
-    "jabba_axis_tolerances",
+    "jabba_axis_tolerances", "jabba_aggregate_points",
 ]
 
 
@@ -91,6 +91,7 @@ def lib() -> C.CDLL:
             L.jabba_digitize_pca.argtypes = [P, P, P, I64, D, D, I32, C.POINTER(Tuning), P, C.POINTER(Dict), P, P,
                                              SZ, P]
             L.jabba_axis_tolerances.argtypes = [D, D, D, C.POINTER(D), C.POINTER(D)]
+            L.jabba_aggregate_points.argtypes = [P, P, P, I64, D, I32, P, I64, P, P, P, P, P, P, SZ, P]
             L.jabba_encode_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_encode.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
             L.jabba_reconstruct_workspace.argtypes = [I64, C.POINTER(SZ)]

@@ -19,6 +19,7 @@ __all__ = [
     "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "reconstruct",
     "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
     "timing_enable", "timing_report", "digitize_stats", "digitize_quality", "kmeans", "axis_tolerances",
+    "aggregate_points",
 ]
 
 
@@ -255,6 +256,35 @@ def digitize(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, ma
                                 _tref(t), _p(symbols), C.byref(d), _p(workspace), workspace.numel(), _stream(stream))
     L.check(rc, "jabba_digitize")
     return symbols, dictionary, workspace
+
+
+def aggregate_points(x: torch.Tensor, y: torch.Tensor, alpha: float, B: int | None = None,
+                     n_points: torch.Tensor | None = None, capacity: int | None = None, workspace=None,
+                     stream=None) -> dict:
+    """Two-stage aggregation of raw 2-D points (jabba_aggregate_points); B=None is one block (the serial
+    greedy).  Returns device tensors labels, cx, cy, count (capacity entries), k (1) and sse (1), and the
+    workspace; enqueued on the stream, no synchronisation."""
+    dev = x.device
+    n = x.numel()
+    if y.numel() != n or x.dtype != torch.float64 or y.dtype != torch.float64:
+        raise ValueError("x and y: float64 tensors of one size")
+    B = max(n, 1) if B is None else int(B)
+    cap = max(n, 1) if capacity is None else int(capacity)
+    if n_points is None:
+        n_points = torch.tensor([n], dtype=torch.int64, device=dev)
+    if workspace is None:
+        workspace = _ws(digitize_workspace_bytes(n, B), dev)
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    cx = torch.zeros(max(cap, 1), dtype=torch.float64, device=dev)
+    cy = torch.zeros(max(cap, 1), dtype=torch.float64, device=dev)
+    count = torch.zeros(max(cap, 1), dtype=torch.int64, device=dev)
+    k = torch.zeros(1, dtype=torch.int64, device=dev)
+    sse = torch.zeros(1, dtype=torch.float64, device=dev)
+    rc = L.lib().jabba_aggregate_points(_p(x), _p(y), _p(n_points), int(n), float(alpha), int(B), _p(labels), cap,
+                                        _p(cx), _p(cy), _p(count), _p(k), _p(sse), _p(workspace), workspace.numel(),
+                                        _stream(stream))
+    L.check(rc, "jabba_aggregate_points")
+    return {"labels": labels[:n], "cx": cx, "cy": cy, "count": count, "k": k, "sse": sse, "workspace": workspace}
 
 
 def axis_tolerances(alpha_len: float, alpha_inc: float, scl: float = 1.0) -> tuple[float, float]:

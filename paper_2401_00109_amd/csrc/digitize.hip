@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ 
     const int64_t base = (int64_t)blockIdx.x * kTreeLeaves + 4 * threadIdx.x;
     double a[4];
     unsigned long long s1 = 0, s2 = 0;
+    bool bad = false;
     const double mean = Pass >= 2 ? ds->mean_inc : 0.0;
     const double mean_len = Pass == 3 && n > 0 ? (double)(int64_t)ds->lsum[0] / (double)n : 0.0;
 #pragma unroll
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ 
                 const unsigned long long l = (unsigned long long)len[idx];
                 s1 += l;
                 s2 += l * l;
+                bad |= !isfinite(v);
             }
         }
         a[i] = v;
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(256) void k_sum_leaves(const int32_t *__restrict__ 
     const double r = block_tree_1024(a[0], a[1], a[2], a[3]);
     if (threadIdx.x == 0) out[blockIdx.x] = r;
     if (Pass == 1) {
+        if (ballot(bad) && lane_id() == 0) set_status(ds->status, kStNonFinite);
         // exact integer partials per workgroup; reduced by k_sum_ints
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) {
@@ -877,6 +880,169 @@ __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, c
     }
 }
 
+// ------------------------------------------------------------ raw 2-D points
+//
+// The aggregation on points as given (no scaling): the key and the gathered
+// coordinates come from the points themselves; the sort, Stage I, Stage II
+// (one column: no length structure) and the label propagation are the
+// digitizer's kernels.  Centers are formed afterwards from the labels.
+struct __align__(16) PointRec {
+    double x;
+    double y;
+};
+static_assert(sizeof(PointRec) == sizeof(PieceRec), "point records share the piece record slots");
+
+__global__ void k_pts_prepare(DigState *ds) {
+    if (threadIdx.x == 0) {
+        ds->sigma_len = 1.0;
+        ds->sigma_inc = 1.0;
+    }
+}
+
+__global__ void k_pts_key(const double *__restrict__ px, const double *__restrict__ py, DigState *ds,
+                          uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, PointRec *__restrict__ rec) {
+    const int64_t n = ds->n;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = px[i], y = py[i];
+        bad |= !(isfinite(x) && isfinite(y));
+        const double xx = x * x;
+        const double yy = y * y;
+        keys[i] = key_bits(__dsqrt_rn(xx + yy));
+        vals[i] = (uint32_t)i;
+        PointRec r;
+        r.x = x;
+        r.y = y;
+        rec[i] = r;
+    }
+    if (ballot(bad) && lane_id() == 0) set_status(ds->status, kStNonFinite);
+}
+
+__global__ void k_pts_gather(const PointRec *__restrict__ rec, DigState *ds, const uint64_t *__restrict__ k0,
+                             const uint64_t *__restrict__ k1, const uint32_t *__restrict__ v0,
+                             const uint32_t *__restrict__ v1, const int32_t *ctl, double *__restrict__ sk,
+                             double *__restrict__ sx, double *__restrict__ sy, uint32_t *__restrict__ perm) {
+    const int64_t n = ds->n;
+    const uint64_t *ks = ctl[0] ? k1 : k0;
+    const uint32_t *vs = ctl[0] ? v1 : v0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t act = 0;
+        for (int d = 0; d < 8; ++d) act += ctl[1 + d] ? 0 : 1;
+        ds->sort_passes = act;
+        if (ctl[32]) set_status(ds->status, kStInternal);
+    }
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = vs[p];
+        const PointRec r = rec[c];
+        sk[p] = key_of_bits(ks[p]);
+        sx[p] = r.x;
+        sy[p] = r.y;
+        perm[p] = c;
+    }
+}
+
+// cluster count, and the sort pairs (label, index) for the per-cluster means
+__global__ void k_pts_pairs(const int64_t *__restrict__ g_count, const uint32_t *__restrict__ gsym, DigState *ds,
+                            const int32_t *__restrict__ labels, int64_t capacity, int64_t *__restrict__ k_out,
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t n = ds->n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t G = *g_count;
+        const int64_t k = G > 0 ? (int64_t)gsym[G] : 0;
+        *k_out = k;
+        if (k > capacity) set_status(ds->status, kStCapacity);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = (uint64_t)(uint32_t)labels[i];
+        vals[i] = (uint32_t)i;
+    }
+}
+
+// run [start, end) of every label in the label-sorted order
+__global__ void k_pts_runs(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+                           const int32_t *__restrict__ ctl, const DigState *ds, int64_t *__restrict__ run_start,
+                           int64_t *__restrict__ run_end) {
+    const int64_t n = ds->n;
+    const uint64_t *keys = ctl[0] ? k1 : k0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = keys[j];
+        if (j == 0 || keys[j - 1] != c) run_start[c] = j;
+        if (j == n - 1 || keys[j + 1] != c) run_end[c] = j + 1;
+    }
+}
+
+// one wavefront per cluster: count, and the means of x and y with the members
+// added one by one in input order (the stable sort keeps that order inside a
+// label), the chain running lane by lane over chunks of 64 members
+__global__ __launch_bounds__(256) void k_pts_centers(const double *__restrict__ px, const double *__restrict__ py,
+                                                     const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
+                                                     const int32_t *__restrict__ ctl, const int64_t *__restrict__ k_p,
+                                                     int64_t capacity, const int64_t *__restrict__ run_start,
+                                                     const int64_t *__restrict__ run_end, double *__restrict__ cx,
+                                                     double *__restrict__ cy, int64_t *__restrict__ count) {
+    const int lane = lane_id();
+    const uint32_t *perm = ctl[0] ? v1 : v0;
+    int64_t k = *k_p;
+    if (k > capacity) k = capacity;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; c < k; c += waves) {
+        const int64_t a = run_start[c], b = run_end[c];
+        double sx = 0.0, sy = 0.0;
+        for (int64_t j0 = a; j0 < b; j0 += kWave) {
+            const int64_t j = j0 + lane;
+            double vx = 0.0, vy = 0.0;
+            if (j < b) {
+                const uint32_t i = perm[j];
+                vx = px[i];
+                vy = py[i];
+            }
+            const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
+            for (int u = 0; u < cnt; ++u) {
+                sx = sx + readlane_f64(vx, u);
+                sy = sy + readlane_f64(vy, u);
+            }
+        }
+        if (lane == 0) {
+            const double m = (double)(b - a);
+            cx[c] = sx / m;
+            cy[c] = sy / m;
+            count[c] = b - a;
+        }
+    }
+}
+
+// level 0 of the SSE's pairwise tree: (x - cx)^2 + (y - cy)^2 in input order
+__global__ __launch_bounds__(256) void k_pts_sse_leaves(const double *__restrict__ px, const double *__restrict__ py,
+                                                        const int32_t *__restrict__ labels, const double *__restrict__ cx,
+                                                        const double *__restrict__ cy, const int64_t *__restrict__ k_p,
+                                                        int64_t capacity, const DigState *ds,
+                                                        double *__restrict__ out) {
+    const int64_t n = ds->n;
+    const bool ok = *k_p <= capacity;
+    const int64_t base = (int64_t)blockIdx.x * kTreeLeaves + 4 * threadIdx.x;
+    double a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t idx = base + i;
+        double v = 0.0;
+        if (ok && idx < n) {
+            const int32_t c = labels[idx];
+            const double dx = px[idx] - cx[c];
+            const double dy = py[idx] - cy[c];
+            const double xx = dx * dx;
+            const double yy = dy * dy;
+            v = xx + yy;
+        }
+        a[i] = v;
+    }
+    const double r = block_tree_1024(a[0], a[1], a[2], a[3]);
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+__global__ void k_pts_sse_out(const double *__restrict__ total, double *__restrict__ sse) {
+    if (threadIdx.x == 0) *sse = *total;
+}
+
 // ------------------------------------------------------------ quality
 //
 // Squared deviation of every sorted piece from its symbol's scaled center.
@@ -1230,6 +1396,114 @@ extern "C" int jabba_digitize(const int32_t *len, const double *inc, const int64
                               const jabba_dict *dict, void *workspace, size_t workspace_bytes, void *stream) {
     return digitize_impl(len, inc, n_pieces, max_pieces, alpha, scl, B, tuning, symbols, dict, kKeyNorm, nullptr,
                          workspace, workspace_bytes, stream);
+}
+
+extern "C" int jabba_aggregate_points(const double *x, const double *y, const int64_t *n_points, int64_t max_points,
+                                      double alpha, int32_t B, int32_t *labels, int64_t capacity, double *cx,
+                                      double *cy, int64_t *count, int64_t *k, double *sse, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+    if (max_points < 0 || B < 1 || !n_points || !k || capacity < 0) return JABBA_EINVAL;
+    if (!(alpha >= 0.0) || !(alpha <= 1.0e150)) return JABBA_EINVAL;
+    if (max_points >= ((int64_t)1 << 31) - 1) return JABBA_EOVERFLOW;
+    if (max_points > 0 && (!x || !y || !labels)) return JABBA_EINVAL;
+    if (capacity > 0 && (!cx || !cy || !count)) return JABBA_EINVAL;
+    const DigWs w0 = carve_digitize(nullptr, max_points, B);
+    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    const DigWs w = carve_digitize(workspace, max_points, B);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = max_points > 0 ? max_points : 1;
+    const int64_t nblk = nblk_of(N, B);
+    int s1w = 4;
+    while (s1w > 1 && (size_t)s1w * sizeof(ActLds) > 65536) s1w >>= 1;
+    const double a2 = alpha * alpha;
+    PointRec *rec = reinterpret_cast<PointRec *>(w.rec);
+    const int64_t *n_live = &w.ds->n;
+
+    JB_LAUNCH(k_dig_prepare, dim3(1), dim3(64), 0, st, w.ds, n_points, max_points);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_pts_prepare, dim3(1), dim3(64), 0, st, w.ds);
+    JB_LAUNCH_CHECK();
+    int rc = radix_sort_init(w.sb, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_pts_key, dim3(grid_for(N)), dim3(256), 0, st, x, y, w.ds, w.sb.keys[0], w.sb.vals[0], rec);
+    JB_LAUNCH_CHECK();
+    rc = radix_global_hist(w.sb, n_live, N, st);
+    if (rc) return rc;
+    rc = radix_sort_pairs(w.sb, n_live, N, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_pts_gather, dim3(grid_for(N)), dim3(256), 0, st, rec, w.ds, w.sb.keys[0], w.sb.keys[1],
+              w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.perm);
+    JB_LAUNCH_CHECK();
+
+    // Stage I
+    JB_LAUNCH(k_cuts, dim3(grid_for(nblk + 1)), dim3(256), 0, st, w.sk, w.ds, (int64_t)B, nblk, w.cuts);
+    JB_LAUNCH_CHECK();
+    const size_t lds = (size_t)s1w * sizeof(ActLds);
+    JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk, w.sk,
+              w.sx, w.sy, alpha, a2, w.glist, w.lab, w.flag, w.sblk);
+    JB_LAUNCH_CHECK();
+    rc = scan_u32_to_u32(w.flag, w.sidx, n_live, N, w.scan_ws, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_compact_starts, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.flag, w.sidx, w.sk, w.sx, w.sy, w.gk,
+              w.gx, w.gy, w.spos, w.g_count);
+    JB_LAUNCH_CHECK();
+
+    // Stage II: one column (scl = 0 switches the length columns off), groups
+    // cut at key gaps larger than alpha
+    rc = radix_sort_init(w.sb, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_col_keys, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.spos, w.slen, w.ds, 0.0, a2,
+              w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH_CHECK();
+    rc = radix_global_hist(w.sb, w.g_count, N, st);
+    if (rc) return rc;
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups");
+    if (rc) return rc;
+    JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
+              w.sb.vals[1], w.sb.ctl, w.gk, w.gx, w.gy, alpha, w.cut, w.ord, w.ck, w.cx, w.cy);
+    JB_LAUNCH_CHECK();
+    rc = scan_u32_to_u32(w.cut, w.cgid, w.g_count, N, w.scan_ws, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_col_groups, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.cut, w.cgid, w.gstart, w.n_groups);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_col_greedy, dim3(grid_for(N * kWave / 4 + 1, 32)), dim3(4 * kWave), 4 * sizeof(ActLds), st,
+              w.n_groups, w.gstart, w.ord, w.ck, w.cx, w.cy, alpha, a2, w.glist, w.own, w.oflag, w.glab, w.gflag);
+    JB_LAUNCH_CHECK();
+    rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, labels);
+    JB_LAUNCH_CHECK();
+
+    // centers: labels sorted stably, one wavefront per cluster
+    rc = radix_sort_init(w.sb, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_pts_pairs, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gsym, w.ds, labels, capacity, k,
+              w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH_CHECK();
+    rc = radix_global_hist(w.sb, n_live, N, st);
+    if (rc) return rc;
+    rc = radix_sort_pairs(w.sb, n_live, N, st, "points");
+    if (rc) return rc;
+    JB_LAUNCH(k_pts_runs, dim3(grid_for(N)), dim3(256), 0, st, w.sb.keys[0], w.sb.keys[1], w.sb.ctl, w.ds, w.ocnt,
+              w.olen);
+    JB_LAUNCH_CHECK();
+    if (capacity > 0) {
+        JB_LAUNCH(k_pts_centers, dim3(grid_for(capacity * kWave, 32)), dim3(256), 0, st, x, y, w.sb.vals[0],
+                  w.sb.vals[1], w.sb.ctl, k, capacity, w.ocnt, w.olen, cx, cy, count);
+        JB_LAUNCH_CHECK();
+    }
+    if (sse) {
+        const int64_t t0 = (N + kTreeLeaves - 1) / kTreeLeaves;
+        JB_LAUNCH(k_pts_sse_leaves, dim3((unsigned)t0), dim3(256), 0, st, x, y, labels, cx, cy, k, capacity, w.ds,
+                  w.tree[0]);
+        JB_LAUNCH_CHECK();
+        double *tot = nullptr;
+        rc = tree_sum_levels(w, N, w.tree[0], st, &tot);
+        if (rc) return rc;
+        JB_LAUNCH(k_pts_sse_out, dim3(1), dim3(64), 0, st, tot, sse);
+        JB_LAUNCH_CHECK();
+    }
+    return JABBA_OK;
 }
 
 extern "C" int jabba_axis_tolerances(double alpha_len, double alpha_inc, double scl_in, double *alpha,

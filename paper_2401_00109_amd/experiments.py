@@ -16,6 +16,11 @@ digitizations the reconstruction MSE and the VQ objective (Eq. sse).
 
     python -m paper_2401_00109_amd.experiments --partitions 1,2,4,8,16,32,64
 
+The Gaussian-blob table (Sec. 7.1, Table 2) runs the two-stage aggregation
+on raw 2-D points:
+
+    python -m paper_2401_00109_amd.experiments --blobs
+
 The digitizer sweep (scl, separate tolerances, PCA key) runs on a compressed
 workload of the input recipe:
 
@@ -165,6 +170,43 @@ def digitizer_sweep(settings, workload_id: int = 2, scale: float = 1.0, seed: in
     return rows
 
 
+def gaussian_blobs(sizes=(5000, 10000), alphas=(0.1, 0.05), blocks=(1, 4, 8), seed: int = 0, repeats: int = 20,
+                   device=None) -> list[dict]:
+    """Table 2 of Sec. 7.1 on the device: the two-stage aggregation of 2-D Gaussian-blob points with M blocks
+    of ceil(N/M) points (M = 1 is the serial greedy aggregation).  Per (alpha, N, M): clusters, SSE (Eq. sse),
+    SSE ratio against M = 1, and the device time of one aggregation (median of `repeats`, HIP events)."""
+    from .inputs import gaussian_blobs as blobs
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    rows = []
+    for alpha in alphas:
+        for n in sizes:
+            x, y = blobs(seed, n)
+            X = torch.from_numpy(x).to(dev)
+            Y = torch.from_numpy(y).to(dev)
+            serial = None
+            for M in blocks:
+                B = -(-n // M)
+                r = api.aggregate_points(X, Y, alpha, B)
+                ws = r["workspace"]
+                times = []
+                for _ in range(repeats):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    api.aggregate_points(X, Y, alpha, B, workspace=ws)
+                    b.record()
+                    torch.cuda.synchronize()
+                    times.append(a.elapsed_time(b))
+                k = int(r["k"].item())
+                sse = float(r["sse"].item())
+                if M == 1:
+                    serial = (k, sse)
+                rows.append({"alpha": alpha, "N": n, "M": M, "B": B, "clusters": k, "sse": sse,
+                             "sse_ratio": sse / serial[1] if serial and serial[1] > 0 else None,
+                             "clusters_serial": serial[0] if serial else None,
+                             "device_ms": float(np.median(times))})
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--partitions", default="1,2,4,8,16,32,64,128")
@@ -172,10 +214,13 @@ def main() -> int:
     ap.add_argument("--kmeans-init", default="aggregation", choices=["aggregation", "spread"])
     ap.add_argument("--kmeans-iter", type=int, default=100)
     ap.add_argument("--sweep", default="", help="digitizer settings as JSON list (runs the sweep instead)")
+    ap.add_argument("--blobs", action="store_true", help="run the Gaussian-blob table (Sec. 7.1) instead")
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--scale", type=float, default=1.0)
     a = ap.parse_args()
-    if a.sweep:
+    if a.blobs:
+        rows = gaussian_blobs()
+    elif a.sweep:
         rows = digitizer_sweep(json.loads(a.sweep), workload_id=a.workload, scale=a.scale)
     else:
         rows = noise_partitions([int(m) for m in a.partitions.split(",")], n=a.n, kmeans_iter=a.kmeans_iter,

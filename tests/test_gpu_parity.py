@@ -201,6 +201,16 @@ def test_digitize_edge_cases(case):
     assert_centers_close(d, od, inc, od.symbols)
 
 
+def test_digitize_nonfinite_status():
+    from paper_2401_00109_amd import _lib
+    w, ol, oi, _ = _pieces(1)
+    bad = oi.copy()
+    bad[5] = np.inf
+    say("digitize with an infinite increment")
+    _, _, st = gpu_digitize(ol, bad, w.alpha, 1.0, 256)
+    assert st == _lib.JABBA_ENONFINITE
+
+
 def test_digitize_capacity_status():
     from paper_2401_00109_amd import _lib
     w, ol, oi, _ = _pieces(1)
