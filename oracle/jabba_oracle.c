@@ -173,6 +173,41 @@ double jo_tree_sum(const double *a, int64_t n)
 }
 
 /*
+ * Series z-normalisation ahead of compression: per series of n points
+ * mean = T(v)/n and std = sqrt(T((v - mean)^2)/n) (population deviation, T the
+ * pairwise sum above), a zero deviation (n = 1, a constant series) replaced
+ * by 1 so the series is only centred; z_i = (v_i - mean)/std.  An empty
+ * series has mean 0 and std 1.
+ */
+int jo_znorm(const double *values, const int64_t *series_off, int64_t n_series, double *mean, double *std_dev,
+             double *out)
+{
+    for (int64_t s = 0; s < n_series; s++) {
+        const int64_t a = series_off[s], n = series_off[s + 1] - a;
+        if (n <= 0) {
+            mean[s] = 0.0;
+            std_dev[s] = 1.0;
+            continue;
+        }
+        double m = jo_tree_sum(values + a, n) / (double)n;
+        double *sq = (double *)malloc((size_t)n * sizeof(double));
+        if (!sq) return JO_ENOMEM;
+        for (int64_t i = 0; i < n; i++) {
+            double d = values[a + i] - m;
+            sq[i] = d * d;
+        }
+        double var = jo_tree_sum(sq, n) / (double)n;
+        free(sq);
+        double sd = sqrt(var);
+        if (!(sd > 0.0)) sd = 1.0;
+        mean[s] = m;
+        std_dev[s] = sd;
+        for (int64_t i = 0; i < n; i++) out[a + i] = (values[a + i] - m) / sd;
+    }
+    return JO_OK;
+}
+
+/*
  * Exact sum rounded once to binary64: the running sum is kept as a list of
  * non-overlapping partials updated with error-free two-sum steps (Shewchuk,
  * "Adaptive precision floating-point arithmetic", 1997), then the partials

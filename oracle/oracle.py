@@ -25,6 +25,7 @@ __all__ = [
     "domains",
     "compress",
     "pca_axis",
+    "znorm",
     "axis_tolerances",
     "aggregate_points",
     "Aggregated",
@@ -131,6 +132,8 @@ def lib():
                                           _f64n, C.c_int64, _i32p, _i64n, _i64n, C.POINTER(C.c_int64), _i64n,
                                           _f64n, _f64n, _f64n, _f64n, _f64n, _i64n, C.POINTER(C.c_int64)]
             L.jo_pca_axis.restype = C.c_int
+            L.jo_znorm.restype = C.c_int
+            L.jo_znorm.argtypes = [_f64p, _i64p, C.c_int64, _f64p, _f64p, _f64p]
             L.jo_aggregate_points.restype = C.c_int64
             L.jo_aggregate_points.argtypes = [_f64p, _f64p, C.c_int64, C.c_double, C.c_int64, C.c_int64, _i32p,
                                               _f64p, _f64p, _i64p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
@@ -265,6 +268,16 @@ class Digitized:
 
 
 KEYS = {"norm": 0, "pca": 1}
+
+
+def znorm(values, series_off):
+    """Per-series z-normalisation (see jo_znorm).  Returns (z f64[total], mean f64[ns], std f64[ns])."""
+    v, so = _f64(values), _i64(series_off)
+    ns = so.size - 1
+    out = np.zeros(max(v.size, 1))
+    m, sd = np.zeros(max(ns, 1)), np.zeros(max(ns, 1))
+    _check(lib().jo_znorm(v, so, ns, m, sd, out), "znorm")
+    return out[:v.size].copy(), m[:ns].copy(), sd[:ns].copy()
 
 
 def pca_axis(length, inc, scl: float = 1.0) -> np.ndarray:

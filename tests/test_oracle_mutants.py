@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "jabba_oracle.c")
 PINS = ["tests/test_oracle_compress.py", "tests/test_oracle_digitize.py", "tests/test_oracle_reconstruct.py",
         "tests/test_oracle_quality.py", "tests/test_oracle_kmeans.py", "tests/test_oracle_pca.py",
-        "tests/test_oracle_points.py"]
+        "tests/test_oracle_points.py", "tests/test_oracle_znorm.py"]
 
 MUTANTS = {
     "square_dropped": ("acc = acc + r * r;", "acc = acc + r;"),
@@ -55,6 +55,10 @@ MUTANTS = {
     "points_key_without_y": ("for (int64_t i = 0; i < N; i++) key[i] = sqrt(x[i] * x[i] + y[i] * y[i]);",
                              "for (int64_t i = 0; i < N; i++) key[i] = fabs(x[i]);"),
     "points_sse_dy_dropped": ("t[i] = dx * dx + dy * dy;", "t[i] = dx * dx;"),
+    "znorm_sample_variance": ("double var = jo_tree_sum(sq, n) / (double)n;",
+                              "double var = jo_tree_sum(sq, n) / (double)(n > 1 ? n - 1 : 1);"),
+    "znorm_not_centred": ("for (int64_t i = 0; i < n; i++) out[a + i] = (values[a + i] - m) / sd;",
+                          "for (int64_t i = 0; i < n; i++) out[a + i] = values[a + i] / sd;"),
     "round_floor": ("return (int64_t)((v + ((i128)1 << (FIX_SHIFT - 1))) >> FIX_SHIFT);",
                     "return (int64_t)(v >> FIX_SHIFT);"),
 }
