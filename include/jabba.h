@@ -146,6 +146,23 @@ int jabba_compress(const double *values, const int64_t *series_off, int64_t n_se
                    int64_t *piece_off, int64_t *n_pieces, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * jabba_compress on the z-normalised series, without writing them: per series
+ * of n points mean = T(v)/n and std = sqrt(T((v - mean)^2)/n) (population
+ * deviation; T the balanced pairwise sum over the series' points in order,
+ * zero-padded to a power of two), a zero deviation (n = 1, a constant series)
+ * replaced by 1 so the series is only centred, an empty series mean 0 and
+ * std 1; the compression then reads every value as (v - mean)/std.  Pieces
+ * are in normalised units (reconstruct, then multiply by std and add mean).
+ *  mean, std_dev: device, n_series entries each, out.
+ * Other arguments, workspace size and device status as jabba_compress; a
+ * series longer than 2^30 points sets JABBA_EOVERFLOW.
+ */
+int jabba_compress_znorm(const double *values, const int64_t *series_off, int64_t n_series, int64_t total_points,
+                         int32_t D, double tol, int32_t max_len, const jabba_tuning *tuning, int32_t *len,
+                         double *inc, int64_t *piece_off, int64_t *n_pieces, double *mean, double *std_dev,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * The same computation launched the plain way: one kernel launch per series
  * (grid = that series' domains, one wavefront per domain, 64 candidate end
  * points per round), no work queue.  Kept as the per-domain-launch baseline

@@ -29,7 +29,7 @@ EXPORTS = [
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
     "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans", "jabba_digitize_pca",
-    "jabba_axis_tolerances", "jabba_aggregate_points",
+    "jabba_axis_tolerances", "jabba_aggregate_points", "jabba_compress_znorm",
 ]
 
 
@@ -85,6 +85,8 @@ def lib() -> C.CDLL:
             L.jabba_status_str.argtypes = [C.c_int]
             L.jabba_compress_workspace.argtypes = [I64, I64, I32, C.POINTER(SZ)]
             L.jabba_compress.argtypes = [P, P, I64, I64, I32, D, I32, C.POINTER(Tuning), P, P, P, P, P, SZ, P]
+            L.jabba_compress_znorm.argtypes = [P, P, I64, I64, I32, D, I32, C.POINTER(Tuning), P, P, P, P, P, P, P,
+                                               SZ, P]
             L.jabba_compress_plain.argtypes = [P, P, P, I64, I32, D, I32, P, P, P, P, P, SZ, P]
             L.jabba_digitize_workspace.argtypes = [I64, I32, C.POINTER(SZ)]
             L.jabba_digitize.argtypes = [P, P, P, I64, D, D, I32, C.POINTER(Tuning), P, C.POINTER(Dict), P, SZ, P]

@@ -89,6 +89,8 @@ class Pieces:
     n_pieces: torch.Tensor   # int64[1]
     max_pieces: int
     workspace: torch.Tensor | None = None
+    mean: torch.Tensor | None = None         # float64[n_series], z-normalised compression only
+    std: torch.Tensor | None = None
 
     def count(self) -> int:
         return int(self.n_pieces.item())
@@ -178,8 +180,11 @@ def workspace_status(ws: torch.Tensor, stream=None) -> int:
 
 def compress(values: torch.Tensor, series_off: torch.Tensor, D: int, tol: float, max_len: int = 0,
              tuning: dict | None = None, max_pieces: int | None = None, out: Pieces | None = None,
-             workspace: torch.Tensor | None = None, stream=None) -> Pieces:
-    """Phase I + II of Alg. 1 on the device (see jabba_compress)."""
+             workspace: torch.Tensor | None = None, stream=None, znorm: bool = False) -> Pieces:
+    """Phase I + II of Alg. 1 on the device (see jabba_compress).
+
+    znorm=True compresses the z-normalised series (jabba_compress_znorm); the per-series mean and deviation
+    are kept as ``out.mean`` and ``out.std``."""
     dev = values.device
     n_series = series_off.numel() - 1
     total = values.numel()
@@ -193,6 +198,15 @@ def compress(values: torch.Tensor, series_off: torch.Tensor, D: int, tol: float,
         workspace = _ws(compress_workspace_bytes(n_series, total, D), dev)
     out.workspace = workspace
     t = tuning_struct(tuning)
+    if znorm:
+        out.mean = torch.empty(max(n_series, 1), dtype=torch.float64, device=dev)
+        out.std = torch.empty(max(n_series, 1), dtype=torch.float64, device=dev)
+        rc = L.lib().jabba_compress_znorm(_p(values), _p(series_off), n_series, total, int(D), float(tol),
+                                          int(max_len), _tref(t), _p(out.len), _p(out.inc), _p(out.piece_off),
+                                          _p(out.n_pieces), _p(out.mean), _p(out.std), _p(workspace),
+                                          workspace.numel(), _stream(stream))
+        L.check(rc, "jabba_compress_znorm")
+        return out
     rc = L.lib().jabba_compress(_p(values), _p(series_off), n_series, total, int(D), float(tol), int(max_len),
                                 _tref(t), _p(out.len), _p(out.inc), _p(out.piece_off), _p(out.n_pieces),
                                 _p(workspace), workspace.numel(), _stream(stream))

@@ -118,6 +118,19 @@ __device__ __forceinline__ double wave_tree_sum(double v) {
     return v;
 }
 
+// Pairwise tree over 1024 leaves (a 256-thread workgroup, every thread calls): 4 adjacent leaves per thread, then the
+// wavefront butterfly, then the four wavefront sums pairwise.
+__device__ __forceinline__ double block_tree_1024(double a0, double a1, double a2, double a3) {
+    __shared__ double ws[4];
+    double v = (a0 + a1) + (a2 + a3);
+    v = wave_tree_sum(v);
+    if (lane_id() == 0) ws[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double r = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);

@@ -108,6 +108,94 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
         p[i] = 0ull;
 }
 
+// Per-series z-normalisation statistics: mean = T(v)/n and
+// std = sqrt(T((v - mean)^2)/n) (population), a zero (or n <= 1) deviation
+// replaced by 1 so the series is only centred.  T is the balanced pairwise sum
+// over the series' points zero-padded to a power of two P, taken as 1024-leaf
+// subtrees aligned to the series start, then a tree over up to 1024 subtree
+// sums, then over up to 1024 of those (zero subtrees add +0 exactly, so this
+// is the tree over P).  One workgroup of 256 threads per series.
+constexpr int64_t kZnMaxBlocks = (int64_t)1 << 20;  // series of up to 2^30 points
+
+template <int Pass>
+__device__ double zn_tree(const double *__restrict__ v, int64_t n, double mean, double *lvl1, double *lvl2) {
+    const int64_t nb = (n + 1023) / 1024;
+    double total = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        double a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t idx = b * 1024 + 4 * threadIdx.x + i;
+            double x = 0.0;
+            if (idx < n) {
+                x = v[idx];
+                if (Pass == 2) {
+                    const double d = x - mean;
+                    x = d * d;
+                }
+            }
+            a[i] = x;
+        }
+        const double r = block_tree_1024(a[0], a[1], a[2], a[3]);
+        if (nb == 1) {
+            total = r;
+            break;
+        }
+        if (threadIdx.x == 0) lvl1[b & 1023] = r;
+        const bool sb_end = (b & 1023) == 1023 || b == nb - 1;
+        if (sb_end) {
+            __syncthreads();
+            const int64_t cnt = (b & 1023) + 1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = 4 * threadIdx.x + i < cnt ? lvl1[4 * threadIdx.x + i] : 0.0;
+            const double sb = block_tree_1024(a[0], a[1], a[2], a[3]);
+            if (nb <= 1024) {
+                total = sb;
+            } else if (threadIdx.x == 0) {
+                lvl2[b >> 10] = sb;
+            }
+            __syncthreads();
+        }
+    }
+    if (nb > 1024) {
+        __syncthreads();
+        const int64_t cnt = (nb + 1023) >> 10;
+        double a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = 4 * threadIdx.x + i < cnt ? lvl2[4 * threadIdx.x + i] : 0.0;
+        total = block_tree_1024(a[0], a[1], a[2], a[3]);
+    }
+    return total;
+}
+
+__global__ __launch_bounds__(256) void k_zn_stats(const double *__restrict__ values,
+                                                  const int64_t *__restrict__ series_off, int64_t n_series,
+                                                  double *__restrict__ zmean, double *__restrict__ zstd,
+                                                  int32_t *status) {
+    __shared__ double lvl1[1024];
+    __shared__ double lvl2[1024];
+    for (int64_t sr = blockIdx.x; sr < n_series; sr += gridDim.x) {
+        const int64_t a = series_off[sr];
+        const int64_t n = series_off[sr + 1] - a;
+        if (n <= 0 || (n + 1023) / 1024 > kZnMaxBlocks) {
+            if (threadIdx.x == 0) {
+                zmean[sr] = 0.0;
+                zstd[sr] = 1.0;
+                if (n > 0) set_status(status, kStOverflow);
+            }
+            continue;
+        }
+        const double mean = zn_tree<1>(values + a, n, 0.0, lvl1, lvl2) / (double)n;
+        const double var = zn_tree<2>(values + a, n, mean, lvl1, lvl2) / (double)n;
+        double sd = __dsqrt_rn(var);
+        if (!(sd > 0.0)) sd = 1.0;
+        if (threadIdx.x == 0) {
+            zmean[sr] = mean;
+            zstd[sr] = sd;
+        }
+    }
+}
+
 __global__ void k_prepare(int32_t *status, int32_t *q_head) {
     if (threadIdx.x == 0) {
         status[0] = 0;
@@ -161,14 +249,17 @@ size_t compress_lds_per_wave() {
     return (size_t)(kWave / W) * (RingShape<W>::R + 1) * sizeof(double);
 }
 
-template <int W>
+// Norm: every value is read as (t - mean[series]) / std[series], so the
+// z-normalised series is compressed without being written anywhere.
+template <int W, bool Norm>
 __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t, const Dom *__restrict__ doms,
                                                    const int32_t *__restrict__ queue,
                                                    const int64_t *__restrict__ n_dom_p, int32_t *__restrict__ q_head,
                                                    int64_t direct_base, int64_t direct_end, double tol2,
                                                    int32_t max_len, int32_t *__restrict__ st_len,
                                                    double *__restrict__ st_inc, int32_t *__restrict__ dom_count,
-                                                   int32_t *status) {
+                                                   int32_t *status, const double *__restrict__ zmean,
+                                                   const double *__restrict__ zstd) {
     constexpr int R = RingShape<W>::R;
     constexpr int Q = RingShape<W>::Q;
     extern __shared__ double ring_all[];
@@ -193,13 +284,22 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     int32_t c0 = 2;
     double S2c = 0.0, S1c = 0.0;  // sums over the terms of candidates below c0
     double pre[Q / W];            // points [le, le + Q), loaded ahead of the refill that stages them
+    double zm = 0.0, zs = 1.0;    // the domain's series mean and deviation (Norm)
 
+    auto value = [&](int64_t p) -> double {
+        if constexpr (Norm) {
+            const double d = t[p] - zm;
+            return d / zs;
+        } else {
+            return t[p];
+        }
+    };
     // requests [le, le + Q): lane j holds points le + r * W + j
     auto prefetch = [&]() {
 #pragma unroll
         for (int r = 0; r < Q / W; ++r) {
             const int64_t p = le + r * W + j;
-            pre[r] = p <= e ? t[p] : 0.0;
+            pre[r] = p <= e ? value(p) : 0.0;
         }
     };
 
@@ -211,7 +311,11 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
         obase = x.start;
         le = x.start;
         np = 0;
-        ts = t[s];
+        if constexpr (Norm) {
+            zm = zmean[x.series];
+            zs = zstd[x.series];
+        }
+        ts = value(s);
         if (j == 0 && !isfinite(ts)) set_status(status, kStNonFinite);
         c0 = 2;
         S2c = 0.0;
@@ -224,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     // output stores still in flight).  Only the exact evaluation of an
     // undecided candidate may reach below the ring, and reads memory there.
     auto at = [&](int64_t p) -> double { return ring[p & (R - 1)]; };
-    auto at_far = [&](int64_t p) -> double { return p >= le - R ? ring[p & (R - 1)] : t[p]; };
+    auto at_far = [&](int64_t p) -> double { return p >= le - R ? ring[p & (R - 1)] : value(p); };
 
     if (direct) {
         const int64_t d = direct_base + wave_g * (kWave / W) + lane / W;
@@ -496,10 +600,16 @@ int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t 
 
 template <int W>
 void launch_w(dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
-              int64_t dbase, int64_t dend, double tol2, int32_t max_len) {
+              int64_t dbase, int64_t dend, double tol2, int32_t max_len, const double *zmean, const double *zstd) {
     const size_t lds = compress_lds_per_wave<W>() * (b.x / kWave);
-    JB_LAUNCH((k_compress<W>), g, b, lds, st, t, w.doms, w.queue, n_dom_p, w.q_head, dbase, dend, tol2,
-                       max_len, w.st_len, w.st_inc, w.dom_count, w.status);
+    if (zmean)
+        JB_LAUNCH_NAMED("k_compress_znorm", (k_compress<W, true>), g, b, lds, st, t, w.doms, w.queue, n_dom_p,
+                        w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
+                        zstd);
+    else
+        JB_LAUNCH_NAMED("k_compress<W>", (k_compress<W, false>), g, b, lds, st, t, w.doms, w.queue, n_dom_p,
+                        w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
+                        zstd);
 }
 
 size_t lds_per_wave(int W) {
@@ -515,15 +625,16 @@ size_t lds_per_wave(int W) {
 }
 
 int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
-                    const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len) {
+                    const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len,
+                    const double *zmean = nullptr, const double *zstd = nullptr) {
     switch (W) {
-        case 1: launch_w<1>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
-        case 2: launch_w<2>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
-        case 4: launch_w<4>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
-        case 8: launch_w<8>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
-        case 16: launch_w<16>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
-        case 32: launch_w<32>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
-        case 64: launch_w<64>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len); break;
+        case 1: launch_w<1>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 2: launch_w<2>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 4: launch_w<4>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 8: launch_w<8>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 16: launch_w<16>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 32: launch_w<32>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 64: launch_w<64>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
         default: return JABBA_EINVAL;
     }
     JB_LAUNCH_CHECK();
@@ -575,6 +686,46 @@ extern "C" int jabba_compress(const double *values, const int64_t *series_off, i
     const int64_t *n_dom_p = w.dom_off + n_series;
     dim3 grid((unsigned)(device_cu_count() * bpc)), block((unsigned)(wpb * kWave));
     rc = launch_compress(W, grid, block, st, values, w, n_dom_p, -1, 0, tol * tol, max_len);
+    if (rc) return rc;
+    return finish(w, n_series, total_points, D, len, inc, piece_off, n_pieces, st);
+}
+
+extern "C" int jabba_compress_znorm(const double *values, const int64_t *series_off, int64_t n_series,
+                                    int64_t total_points, int32_t D, double tol, int32_t max_len,
+                                    const jabba_tuning *tuning, int32_t *len, double *inc, int64_t *piece_off,
+                                    int64_t *n_pieces, double *mean, double *std_dev, void *workspace,
+                                    size_t workspace_bytes, void *stream) {
+    int rc = validate(values, series_off, n_series, total_points, D, tol, max_len, len, inc, piece_off, n_pieces);
+    if (rc) return rc;
+    if (n_series > 0 && (!mean || !std_dev)) return JABBA_EINVAL;
+    CompressWs w0 = carve_compress(nullptr, n_series, total_points, D);
+    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    CompressWs w = carve_compress(workspace, n_series, total_points, D);
+    hipStream_t st = (hipStream_t)stream;
+    int W = kDefaultW, wpb = kDefaultWavesPerBlock, bpc = kDefaultBlocksPerCu;
+    if (tuning) {
+        if (tuning->lanes_per_domain) W = tuning->lanes_per_domain;
+        if (tuning->waves_per_block) wpb = tuning->waves_per_block;
+        if (tuning->blocks_per_cu) bpc = tuning->blocks_per_cu;
+    }
+    if (wpb < 1 || wpb > 16 || bpc < 1 || bpc > 32) return JABBA_EINVAL;
+    if (W != 1 && W != 2 && W != 4 && W != 8 && W != 16 && W != 32 && W != 64) return JABBA_EINVAL;
+    const int max_wpb = (int)(65536 / lds_per_wave(W));
+    if (wpb > max_wpb) wpb = max_wpb < 1 ? 1 : max_wpb;
+    rc = domain_table(w, series_off, n_series, total_points, D, true, st);
+    if (rc) return rc;
+    if (n_series > 0) {
+        int64_t blocks = n_series;
+        const int64_t cap = (int64_t)device_cu_count() * 16;
+        if (blocks > cap) blocks = cap;
+        JB_LAUNCH(k_zn_stats, dim3((unsigned)blocks), dim3(256), 0, st, values, series_off, n_series, mean, std_dev,
+                  w.status);
+        JB_LAUNCH_CHECK();
+    }
+    const int64_t *n_dom_p = w.dom_off + n_series;
+    dim3 grid((unsigned)(device_cu_count() * bpc)), block((unsigned)(wpb * kWave));
+    rc = launch_compress(W, grid, block, st, values, w, n_dom_p, -1, 0, tol * tol, max_len, n_series > 0 ? mean : nullptr,
+                         std_dev);
     if (rc) return rc;
     return finish(w, n_series, total_points, D, len, inc, piece_off, n_pieces, st);
 }

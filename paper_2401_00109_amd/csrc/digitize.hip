@@ -52,18 +52,6 @@ __global__ void k_dig_prepare(DigState *ds, const int64_t *n_dev, int64_t n_max)
     }
 }
 
-// Pairwise tree over 1024 leaves: 4 adjacent leaves per thread, then the
-// wavefront butterfly, then the four wavefront sums pairwise.
-__device__ __forceinline__ double block_tree_1024(double a0, double a1, double a2, double a3) {
-    __shared__ double ws[4];
-    double v = (a0 + a1) + (a2 + a3);
-    v = wave_tree_sum(v);
-    if (lane_id() == 0) ws[threadIdx.x / kWave] = v;
-    __syncthreads();
-    double r = (ws[0] + ws[1]) + (ws[2] + ws[3]);
-    __syncthreads();
-    return r;
-}
 
 // level 0: leaves are inc (pass 1), (inc - mean_inc)^2 (pass 2) or
 // (len - mean_len)*(inc - mean_inc) (pass 3, the PCA key's covariance); pass 1

@@ -44,7 +44,7 @@ def timing_name(kernel: str) -> str:
         return kernel.split("(")[0][-60:]
     base, targs = m.group(1), (m.group(2) or "")
     if base == "k_compress":
-        return "k_compress<W>"
+        return "k_compress_znorm" if ("true" in targs or "(bool)1" in targs) else "k_compress<W>"
     if base == "k_onesweep":
         return base + ("_groups" if targs == "<1>" else "")
     if base == "k_key":

@@ -27,7 +27,7 @@ def to_dev(a, dtype=None):
     return t.to(DEV)
 
 
-def gpu_compress(values, series_off, D, tol, max_len=0, tuning=None, plain=False):
+def gpu_compress(values, series_off, D, tol, max_len=0, tuning=None, plain=False, znorm=False):
     import paper_2401_00109_amd as J
     T = torch()
     v = to_dev(np.asarray(values, np.float64))
@@ -35,10 +35,13 @@ def gpu_compress(values, series_off, D, tol, max_len=0, tuning=None, plain=False
     if plain:
         p = J.compress_plain(v, so, np.asarray(series_off, np.int64), D, tol, max_len)
     else:
-        p = J.compress(v, so, D, tol, max_len, tuning=tuning)
+        p = J.compress(v, so, D, tol, max_len, tuning=tuning, znorm=znorm)
     T.cuda.synchronize()
     st = J.workspace_status(p.workspace)
     ln, inc, po = p.host()
+    if znorm:
+        ns = len(series_off) - 1
+        return ln, inc, po, st, p.mean[:ns].cpu().numpy(), p.std[:ns].cpu().numpy()
     return ln, inc, po, st
 
 
