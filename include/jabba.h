@@ -84,7 +84,12 @@ typedef struct jabba_tuning {
     int32_t stage1_waves;     /* digitize Stage I: wavefronts per workgroup (one block
                                  of sorted pieces per wavefront), 1..16 (halved until
                                  the workgroup's LDS fits in 64 KB, i.e. at most 4)     */
-    int32_t reserved[4];
+    int32_t segment_intervals; /* compress: domains are compressed as segments of this
+                                 many intervals in parallel, then repaired into the
+                                 domain's own pieces; >= 32, or -1 for whole domains;
+                                 0 = default: segments of 128 when there are fewer
+                                 than 16 domains per compute unit, else whole domains  */
+    int32_t reserved[3];
 } jabba_tuning;
 
 /*

@@ -35,7 +35,7 @@ EXPORTS = [
 
 class Tuning(C.Structure):
     _fields_ = [("lanes_per_domain", C.c_int32), ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("stage1_waves", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("stage1_waves", C.c_int32), ("segment_intervals", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Dict(C.Structure):

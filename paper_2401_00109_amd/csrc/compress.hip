@@ -22,18 +22,16 @@
 // is persistent and balances uneven series.
 #include "common.h"
 #include "compress_filter.h"
+#include "compress_repair.h"
 
 namespace jabba {
 
-struct Dom {
-    int64_t start;
-    int32_t nint;
-    int32_t series;
-};
+constexpr int32_t kMinSegment = 32;       // smallest segment (workspace sizing)
+constexpr int32_t kDefaultSegment = 128;  // intervals per segment by default
 
 namespace {
 
-__global__ void k_series_domains(const int64_t *__restrict__ series_off, int64_t n_series, int32_t D,
+__global__ void k_series_domains(const int64_t *__restrict__ series_off, int64_t n_series, int32_t D, int32_t G,
                                  int32_t *__restrict__ ndom, int32_t *status) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_series) return;
@@ -42,37 +40,74 @@ __global__ void k_series_domains(const int64_t *__restrict__ series_off, int64_t
         set_status(status, kStOverflow);
         n = 0;
     }
-    ndom[s] = n >= 2 ? (int32_t)((n - 1 + D - 1) / D) : 0;
+    if (n < 2) {
+        ndom[s] = 0;
+        return;
+    }
+    const int64_t nd = (n - 1 + D - 1) / D;
+    const int32_t last = (int32_t)((n - 1) - (nd - 1) * D);
+    ndom[s] = (int32_t)((nd - 1) * n_segments(D, G) + n_segments(last, G));
 }
 
+// One wavefront per series; its lanes write the series' work units (every
+// domain of D intervals, the last one shorter, each cut into segments of G).
 __global__ void k_fill_domains(const int64_t *__restrict__ series_off, const int64_t *__restrict__ dom_off,
-                               int64_t n_series, int32_t D, Dom *__restrict__ doms,
+                               int64_t n_series, int32_t D, int32_t G, Dom *__restrict__ doms,
                                unsigned long long *__restrict__ len_hist) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long full = 0;
-    if (s < n_series) {
+    const int lane = lane_id();
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
         const int64_t lo = series_off[s], n = series_off[s + 1] - series_off[s];
+        if (n < 2) continue;
         const int64_t d0 = dom_off[s];
-        int64_t d = 0;
-        for (int64_t a = 0; a + 1 < n; a += D, ++d) {
-            const int64_t b = a + D < n - 1 ? a + D : n - 1;
+        const int64_t nd = (n - 1 + D - 1) / D;
+        const int32_t last = (int32_t)((n - 1) - (nd - 1) * D);
+        const int32_t spd = n_segments(D, G);  // segments of a full domain
+        const int64_t n_full = (nd - 1) * spd;
+        const int32_t nsl = n_segments(last, G);
+        unsigned long long full = 0, fullseg = 0;
+        for (int64_t u = lane; u < n_full + nsl; u += kWave) {
+            int64_t dom;
+            int32_t k, ns, nint_d;
+            if (u < n_full) {
+                dom = u / spd;
+                k = (int32_t)(u - dom * spd);
+                ns = spd;
+                nint_d = D;
+            } else {
+                dom = nd - 1;
+                k = (int32_t)(u - n_full);
+                ns = nsl;
+                nint_d = last;
+            }
+            const int64_t a = dom * D + (int64_t)k * (ns > 1 ? G : 0);
+            const int64_t b = k == ns - 1 ? dom * D + nint_d : a + G;
             Dom x;
             x.start = lo + a;
             x.nint = (int32_t)(b - a);
             x.series = (int32_t)s;
-            doms[d0 + d] = x;
+            x.seg = k;
+            x.nseg = ns;
+            doms[d0 + u] = x;
             if (len_hist) {
                 if (x.nint == D)
                     ++full;
+                else if (x.nint == G)
+                    ++fullseg;
                 else
                     atomicAdd(&len_hist[D - x.nint], 1ull);
             }
         }
-    }
-    // full-length domains all fall in bin 0: one atomic per wavefront
+        if (len_hist) {
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) full += __shfl_xor(full, m);
-    if (len_hist && lane_id() == 0 && full) atomicAdd(&len_hist[0], full);
+            for (int m = 1; m < 64; m <<= 1) {
+                full += __shfl_xor(full, m);
+                fullseg += __shfl_xor(fullseg, m);
+            }
+            if (lane == 0 && full) atomicAdd(&len_hist[0], full);
+            if (lane == 0 && fullseg) atomicAdd(&len_hist[D - G], fullseg);
+        }
+    }
 }
 
 // queue position by descending length (counting sort; order inside a bin is
@@ -333,7 +368,7 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     if (direct) {
         const int64_t d = direct_base + wave_g * (kWave / W) + lane / W;
         exhausted = true;
-        if (d < direct_end) start_domain((int32_t)d);
+        if (d < direct_end && d < n_dom) start_domain((int32_t)d);
     }
 
     for (;;) {
@@ -466,15 +501,67 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     }
 }
 
+// ------------------------------------------------------------ segment repair
+//
+// Segments were compressed as if each were a domain, so every segment's
+// chain of pieces starts at the segment start and its last piece is cut at
+// the segment end.  The domain's true chain is recovered per domain, one lane
+// walking its segments in order: from the true chain's position it takes the
+// greedy's own pieces until it lands on a start of the segment's chain (from
+// there the two chains coincide, being the same greedy from the same point),
+// keeps the segment's pieces up to its last one, and recomputes that last
+// piece without the segment end.  Each segment's staging region is rewritten
+// in place to hold exactly the true pieces that start inside it, so the
+// compaction that follows is the one of the plain domains.  Decisions come
+// from the same certified filter with the same exact fallback as the
+// kernel's, so they are the definition's.
+template <bool Norm>
+struct Values {
+    const double *t;
+    double zm, zs;
+    __device__ double operator()(int64_t p) const {
+        if constexpr (Norm) {
+            const double d = t[p] - zm;
+            return d / zs;
+        } else {
+            return t[p];
+        }
+    }
+};
+
+template <bool Norm>
+__global__ void k_repair(const Dom *__restrict__ doms, const int64_t *__restrict__ n_dom_p,
+                         const double *__restrict__ t, const double *__restrict__ zmean,
+                         const double *__restrict__ zstd, double tol2, int32_t max_len, int32_t *__restrict__ st_len,
+                         double *__restrict__ st_inc, int32_t *__restrict__ dom_count, int32_t *__restrict__ first,
+                         int32_t *status) {
+    const int64_t n_dom = *n_dom_p;
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n_dom;
+         d += (int64_t)gridDim.x * blockDim.x) {
+        const Dom x = doms[d];
+        if (x.seg != 0 || x.nseg <= 1) continue;
+        Values<Norm> v{t, 0.0, 1.0};
+        if constexpr (Norm) {
+            v.zm = zmean[x.series];
+            v.zs = zstd[x.series];
+        }
+        bool nonfinite = false;
+        if (repair_domain(v, doms, d, tol2, max_len, st_len, st_inc, dom_count, first, &nonfinite))
+            set_status(status, kStInternal);
+        if (nonfinite) set_status(status, kStNonFinite);
+    }
+}
+
 __global__ void k_compact(const Dom *__restrict__ doms, const int64_t *__restrict__ n_dom_p,
                           const int32_t *__restrict__ dom_count, const int64_t *__restrict__ dom_poff,
                           const int32_t *__restrict__ st_len, const double *__restrict__ st_inc,
-                          int32_t *__restrict__ len, double *__restrict__ inc) {
+                          const int32_t *__restrict__ first, int32_t *__restrict__ len, double *__restrict__ inc) {
     const int64_t n_dom = *n_dom_p;
     const int lane = lane_id();
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t d = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; d < n_dom; d += waves) {
-        const int64_t src = doms[d].start;
+        const Dom x = doms[d];
+        const int64_t src = x.start + (x.nseg > 1 ? first[d] : 0);
         const int64_t dst = dom_poff[d];
         const int32_t cnt = dom_count[d];
         for (int32_t i = lane; i < cnt; i += kWave) {
@@ -503,6 +590,7 @@ struct CompressWs {
     int64_t *bin_off;
     int32_t *queue;
     int32_t *dom_count;
+    int32_t *dom_first;
     int64_t *dom_poff;
     int32_t *st_len;
     double *st_inc;
@@ -510,8 +598,10 @@ struct CompressWs {
     size_t bytes;
 };
 
+// work units (segments of domains) for any segment length >= kMinSegment
 int64_t max_domains(int64_t n_series, int64_t total_points, int32_t D) {
-    return total_points / D + n_series + 1;
+    const int64_t G = D < kMinSegment ? D : kMinSegment;
+    return total_points / G + total_points / D + n_series + 1;
 }
 
 CompressWs carve_compress(void *ws, int64_t n_series, int64_t total_points, int32_t D) {
@@ -527,6 +617,7 @@ CompressWs carve_compress(void *ws, int64_t n_series, int64_t total_points, int3
     w.bin_off = c.take<int64_t>((size_t)D + 3);
     w.queue = c.take<int32_t>(md);
     w.dom_count = c.take<int32_t>(md);
+    w.dom_first = c.take<int32_t>(md);
     w.dom_poff = c.take<int64_t>(md + 1);
     w.st_len = c.take<int32_t>(total_points);
     w.st_inc = c.take<double>(total_points);
@@ -549,12 +640,12 @@ int validate(const double *values, const int64_t *series_off, int64_t n_series, 
 }
 
 int domain_table(const CompressWs &w, const int64_t *series_off, int64_t n_series, int64_t total_points, int32_t D,
-                 bool want_queue, hipStream_t st) {
+                 int32_t G, bool want_queue, hipStream_t st) {
     const int64_t md = max_domains(n_series, total_points, D);
     const unsigned sb = (unsigned)((n_series + 255) / 256 > 0 ? (n_series + 255) / 256 : 1);
     JB_LAUNCH(k_prepare, dim3(1), dim3(64), 0, st, w.status, w.q_head);
     JB_LAUNCH_CHECK();
-    JB_LAUNCH(k_series_domains, dim3(sb), dim3(256), 0, st, series_off, n_series, D, w.ndom, w.status);
+    JB_LAUNCH(k_series_domains, dim3(sb), dim3(256), 0, st, series_off, n_series, D, G, w.ndom, w.status);
     JB_LAUNCH_CHECK();
     int rc = scan_i32_to_i64(w.ndom, w.dom_off, nullptr, n_series, w.scan_ws, st);
     if (rc) return rc;
@@ -563,8 +654,14 @@ int domain_table(const CompressWs &w, const int64_t *series_off, int64_t n_serie
                            (int64_t)D + 2);
         JB_LAUNCH_CHECK();
     }
-    JB_LAUNCH(k_fill_domains, dim3(sb), dim3(256), 0, st, series_off, w.dom_off, n_series, D, w.doms,
-                       want_queue ? w.len_hist : nullptr);
+    {
+        int64_t fb = (n_series * kWave + 255) / 256;
+        const int64_t cap = (int64_t)device_cu_count() * 16;
+        if (fb > cap) fb = cap;
+        if (fb < 1) fb = 1;
+        JB_LAUNCH(k_fill_domains, dim3((unsigned)fb), dim3(256), 0, st, series_off, w.dom_off, n_series, D, G, w.doms,
+                  want_queue ? w.len_hist : nullptr);
+    }
     JB_LAUNCH_CHECK();
     if (want_queue) {
         rc = scan_i64_to_i64(reinterpret_cast<const int64_t *>(w.len_hist), w.bin_off, nullptr, (int64_t)D + 1,
@@ -590,7 +687,7 @@ int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t 
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     JB_LAUNCH(k_compact, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, n_dom_p, w.dom_count, w.dom_poff,
-                       w.st_len, w.st_inc, len, inc);
+                       w.st_len, w.st_inc, w.dom_first, len, inc);
     JB_LAUNCH_CHECK();
     JB_LAUNCH(k_piece_off, dim3((unsigned)((n_series + 1 + 255) / 256)), dim3(256), 0, st, w.dom_off,
                        w.dom_poff, n_series, piece_off, n_pieces);
@@ -612,6 +709,64 @@ void launch_w(dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs 
                         zstd);
 }
 
+int launch_repair(const CompressWs &w, const int64_t *n_dom_p, int64_t n_series, int64_t total_points, int32_t D,
+                  const double *t, double tol2, int32_t max_len, const double *zmean, const double *zstd,
+                  hipStream_t st) {
+    const int64_t md = max_domains(n_series, total_points, D);
+    int64_t blocks = (md + 255) / 256;
+    const int64_t cap = (int64_t)device_cu_count() * 8;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    if (zmean)
+        JB_LAUNCH(k_repair<true>, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, n_dom_p, t, zmean, zstd, tol2,
+                  max_len, w.st_len, w.st_inc, w.dom_count, w.dom_first, w.status);
+    else
+        JB_LAUNCH(k_repair<false>, dim3((unsigned)blocks), dim3(256), 0, st, w.doms, n_dom_p, t, zmean, zstd, tol2,
+                  max_len, w.st_len, w.st_inc, w.dom_count, w.dom_first, w.status);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
+
+int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
+                    const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len,
+                    const double *zmean, const double *zstd);
+
+// segments: one group per work unit, assigned statically (segments are of
+// nearly equal length, so no queue is needed)
+int launch_segments(int W, int wpb, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
+                    int64_t n_series, int64_t total_points, int32_t D, double tol2, int32_t max_len,
+                    const double *zmean, const double *zstd) {
+    const int64_t md = max_domains(n_series, total_points, D);
+    const int64_t groups_per_block = (int64_t)wpb * (kWave / W);
+    int64_t blocks = (md + groups_per_block - 1) / groups_per_block;
+    if (blocks < 1) blocks = 1;
+    if (blocks > ((int64_t)1 << 31) - 1) return JABBA_EOVERFLOW;
+    return launch_compress(W, dim3((unsigned)blocks), dim3((unsigned)(wpb * kWave)), st, t, w, n_dom_p, 0, md, tol2,
+                           max_len, zmean, zstd);
+}
+
+// Segment length from the tuning: negative = whole domains; 0 = the default,
+// which segments only when there are too few domains to occupy the device
+// (fewer than kFewDomainsPerCu per compute unit; with many domains the
+// repair's sequential walks cost more than the extra parallelism saves).
+constexpr int64_t kFewDomainsPerCu = 16;
+
+int32_t segment_of(const jabba_tuning *tuning, int64_t n_series, int64_t total_points, int32_t D, int *rc) {
+    int32_t G = kDefaultSegment;
+    if (tuning && tuning->segment_intervals) {
+        G = tuning->segment_intervals;
+    } else {
+        const int64_t domains = total_points / D + n_series;
+        if (domains >= kFewDomainsPerCu * (int64_t)device_cu_count()) return D;
+    }
+    if (G < 0) return D;
+    if (G < kMinSegment) {
+        *rc = JABBA_EINVAL;
+        return D;
+    }
+    return G < D ? G : D;
+}
+
 size_t lds_per_wave(int W) {
     switch (W) {
         case 1: return compress_lds_per_wave<1>();
@@ -626,7 +781,7 @@ size_t lds_per_wave(int W) {
 
 int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
                     const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len,
-                    const double *zmean = nullptr, const double *zstd = nullptr) {
+                    const double *zmean, const double *zstd) {
     switch (W) {
         case 1: launch_w<1>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
         case 2: launch_w<2>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
@@ -681,12 +836,20 @@ extern "C" int jabba_compress(const double *values, const int64_t *series_off, i
     // a workgroup's ring buffers stay within 64 KB of LDS
     const int max_wpb = (int)(65536 / lds_per_wave(W));
     if (wpb > max_wpb) wpb = max_wpb < 1 ? 1 : max_wpb;
-    rc = domain_table(w, series_off, n_series, total_points, D, true, st);
+    const int32_t G = segment_of(tuning, n_series, total_points, D, &rc);
+    if (rc) return rc;
+    rc = domain_table(w, series_off, n_series, total_points, D, G, G >= D, st);
     if (rc) return rc;
     const int64_t *n_dom_p = w.dom_off + n_series;
-    dim3 grid((unsigned)(device_cu_count() * bpc)), block((unsigned)(wpb * kWave));
-    rc = launch_compress(W, grid, block, st, values, w, n_dom_p, -1, 0, tol * tol, max_len);
+    rc = G < D ? launch_segments(W, wpb, st, values, w, n_dom_p, n_series, total_points, D, tol * tol, max_len,
+                                 nullptr, nullptr)
+               : launch_compress(W, dim3((unsigned)(device_cu_count() * bpc)), dim3((unsigned)(wpb * kWave)), st,
+                                 values, w, n_dom_p, -1, 0, tol * tol, max_len, nullptr, nullptr);
     if (rc) return rc;
+    if (G < D) {
+        rc = launch_repair(w, n_dom_p, n_series, total_points, D, values, tol * tol, max_len, nullptr, nullptr, st);
+        if (rc) return rc;
+    }
     return finish(w, n_series, total_points, D, len, inc, piece_off, n_pieces, st);
 }
 
@@ -712,7 +875,9 @@ extern "C" int jabba_compress_znorm(const double *values, const int64_t *series_
     if (W != 1 && W != 2 && W != 4 && W != 8 && W != 16 && W != 32 && W != 64) return JABBA_EINVAL;
     const int max_wpb = (int)(65536 / lds_per_wave(W));
     if (wpb > max_wpb) wpb = max_wpb < 1 ? 1 : max_wpb;
-    rc = domain_table(w, series_off, n_series, total_points, D, true, st);
+    const int32_t G = segment_of(tuning, n_series, total_points, D, &rc);
+    if (rc) return rc;
+    rc = domain_table(w, series_off, n_series, total_points, D, G, G >= D, st);
     if (rc) return rc;
     if (n_series > 0) {
         int64_t blocks = n_series;
@@ -723,10 +888,16 @@ extern "C" int jabba_compress_znorm(const double *values, const int64_t *series_
         JB_LAUNCH_CHECK();
     }
     const int64_t *n_dom_p = w.dom_off + n_series;
-    dim3 grid((unsigned)(device_cu_count() * bpc)), block((unsigned)(wpb * kWave));
-    rc = launch_compress(W, grid, block, st, values, w, n_dom_p, -1, 0, tol * tol, max_len, n_series > 0 ? mean : nullptr,
-                         std_dev);
+    const double *zm = n_series > 0 ? mean : nullptr;
+    rc = G < D ? launch_segments(W, wpb, st, values, w, n_dom_p, n_series, total_points, D, tol * tol, max_len, zm,
+                                 std_dev)
+               : launch_compress(W, dim3((unsigned)(device_cu_count() * bpc)), dim3((unsigned)(wpb * kWave)), st,
+                                 values, w, n_dom_p, -1, 0, tol * tol, max_len, zm, std_dev);
     if (rc) return rc;
+    if (G < D && n_series > 0) {
+        rc = launch_repair(w, n_dom_p, n_series, total_points, D, values, tol * tol, max_len, mean, std_dev, st);
+        if (rc) return rc;
+    }
     return finish(w, n_series, total_points, D, len, inc, piece_off, n_pieces, st);
 }
 
@@ -742,7 +913,7 @@ extern "C" int jabba_compress_plain(const double *values, const int64_t *series_
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
     CompressWs w = carve_compress(workspace, n_series, total_points, D);
     hipStream_t st = (hipStream_t)stream;
-    rc = domain_table(w, series_off, n_series, total_points, D, false, st);
+    rc = domain_table(w, series_off, n_series, total_points, D, D, false, st);
     if (rc) return rc;
     const int64_t *n_dom_p = w.dom_off + n_series;
     int64_t d0 = 0;
@@ -751,7 +922,7 @@ extern "C" int jabba_compress_plain(const double *values, const int64_t *series_
         const int64_t nd = n >= 2 ? (n - 1 + D - 1) / D : 0;
         if (nd > 0) {
             rc = launch_compress(64, dim3((unsigned)nd), dim3(kWave), st, values, w, n_dom_p, d0, d0 + nd,
-                                 tol * tol, max_len);
+                                 tol * tol, max_len, nullptr, nullptr);
             if (rc) return rc;
         }
         d0 += nd;

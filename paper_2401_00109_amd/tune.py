@@ -23,10 +23,11 @@ from . import api
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "jabba", "tuning.json")
 
 COMPRESS_SPACE = [
-    {"lanes_per_domain": w, "waves_per_block": wpb, "blocks_per_cu": bpc}
+    {"lanes_per_domain": w, "waves_per_block": wpb, "blocks_per_cu": bpc, "segment_intervals": g}
     for w in (1, 2, 4, 8, 16)
     for wpb in (1, 2, 4)
     for bpc in (2, 4, 8, 16)
+    for g in (-1, 64, 128, 256)
 ]
 STAGE1_SPACE = [1, 2, 4]  # larger values are clamped to 4 by the library
 

@@ -75,6 +75,38 @@ def test_compress_lane_width_never_changes_results(W):
         np.testing.assert_array_equal(po, opo)
 
 
+@pytest.mark.parametrize("G", [-1, 32, 57, 128, 999, 5000])
+def test_compress_segment_length_never_changes_results(G):
+    # domains compressed as segments of G intervals and repaired (G = -1: whole domains)
+    for wid in (2, 3):
+        w = _workload(wid)
+        ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+        for W in (1, 4):
+            say(f"compress workload {wid} segments of {G} intervals, W={W}")
+            ln, inc, po, st = gpu_compress(w.values, w.series_off, w.D, w.tol,
+                                           tuning={"segment_intervals": G, "lanes_per_domain": W})
+            assert st == 0
+            np.testing.assert_array_equal(ln, ol)
+            np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+            np.testing.assert_array_equal(po, opo)
+
+
+def test_compress_segments_with_limits_and_ties():
+    # tol = 0, max_len, constant and straight stretches: pieces longer than the segments
+    rng = np.random.default_rng(5)
+    vals = np.concatenate([np.cumsum(rng.standard_normal(6000)), 0.25 * np.arange(3000.0), np.full(2000, 1.5),
+                           np.repeat(rng.integers(-3, 4, 150).astype(np.float64), 20)])
+    off = np.array([0, 6000, 9000, 11000, 14000], np.int64)
+    for tol, max_len in [(0.0, 0), (0.5, 5), (5.0, 0), (5.0, 40)]:
+        ol, oi, opo = O.compress(vals, off, 2500, tol, max_len)
+        for G in (32, 100):
+            say(f"compress segments of {G}, tol={tol} max_len={max_len}")
+            ln, inc, po, st = gpu_compress(vals, off, 2500, tol, max_len, tuning={"segment_intervals": G})
+            assert st == 0
+            np.testing.assert_array_equal(ln, ol)
+            np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+
+
 def test_compress_plain_launches_equal_batched():
     w = _workload(3)
     say("compress plain per-series launches")

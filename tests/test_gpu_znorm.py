@@ -48,6 +48,13 @@ def test_znorm_lane_width_never_changes_results(W):
     _check(v, so, 400, 0.1, tuning={"lanes_per_domain": W})
 
 
+@pytest.mark.parametrize("G", [-1, 32, 77])
+def test_znorm_segments_never_change_results(G):
+    v, so = _raw(10, [5000] * 6 + [123])
+    say(f"znorm compress, segments of {G} intervals")
+    _check(v, so, 2000, 0.05, tuning={"segment_intervals": G})
+
+
 def test_znorm_degenerate_series():
     v = np.concatenate([np.full(500, 7.0), [3.0], 2.0 + 0.25 * np.arange(800)])
     so = np.array([0, 500, 501, 501, 1301], np.int64)
