@@ -87,8 +87,9 @@ typedef struct jabba_tuning {
     int32_t segment_intervals; /* compress: domains are compressed as segments of this
                                  many intervals in parallel, then repaired into the
                                  domain's own pieces; >= 32, or -1 for whole domains;
-                                 0 = default: segments of 128 when there are fewer
-                                 than 16 domains per compute unit, else whole domains  */
+                                 0 = default: segments of 128 when the domains are
+                                 fewer than a quarter of the compute units, else
+                                 whole domains                                          */
     int32_t reserved[3];
 } jabba_tuning;
 

@@ -746,10 +746,11 @@ int launch_segments(int W, int wpb, hipStream_t st, const double *t, const Compr
 }
 
 // Segment length from the tuning: negative = whole domains; 0 = the default,
-// which segments only when there are too few domains to occupy the device
-// (fewer than kFewDomainsPerCu per compute unit; with many domains the
-// repair's sequential walks cost more than the extra parallelism saves).
-constexpr int64_t kFewDomainsPerCu = 16;
+// which segments only when the domains are fewer than a quarter of the
+// compute units.  With more domains the repair's sequential walks (the two
+// chains can stay out of step for hundreds of rounds on noisy data) cost
+// more than the extra parallelism saves; the autotuner tries both.
+constexpr int64_t kFewDomainsDivisor = 4;
 
 int32_t segment_of(const jabba_tuning *tuning, int64_t n_series, int64_t total_points, int32_t D, int *rc) {
     int32_t G = kDefaultSegment;
@@ -757,7 +758,7 @@ int32_t segment_of(const jabba_tuning *tuning, int64_t n_series, int64_t total_p
         G = tuning->segment_intervals;
     } else {
         const int64_t domains = total_points / D + n_series;
-        if (domains >= kFewDomainsPerCu * (int64_t)device_cu_count()) return D;
+        if (domains * kFewDomainsDivisor >= (int64_t)device_cu_count()) return D;
     }
     if (G < 0) return D;
     if (G < kMinSegment) {

@@ -180,10 +180,12 @@ def main() -> int:
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--rates", default="0.25,0.5,0.9", help="fractions of the closed-loop saturation rate")
     ap.add_argument("--max-series", type=int, default=256)
+    ap.add_argument("--tuning", default=None, help="JSON dict of jabba_tuning fields for the compression")
     a = ap.parse_args()
     dev = torch.device("cuda", 0)
     d = build_resident_dictionary(dev)
-    srv = Server(d, slots=a.slots, max_series=a.max_series, device=dev)
+    srv = Server(d, slots=a.slots, max_series=a.max_series, tuning=json.loads(a.tuning) if a.tuning else None,
+                 device=dev)
     # closed loop (everything queued at t=0) -> saturation rate
     warm = request_stream(1, a.warmup, 0.0, max_series=a.max_series, first_id=10_000_000)
     srv.run(warm, realtime=False)
