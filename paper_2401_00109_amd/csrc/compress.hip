@@ -54,8 +54,14 @@ __global__ void k_series_domains(const int64_t *__restrict__ series_off, int64_t
 __global__ void k_fill_domains(const int64_t *__restrict__ series_off, const int64_t *__restrict__ dom_off,
                                int64_t n_series, int32_t D, int32_t G, Dom *__restrict__ doms,
                                unsigned long long *__restrict__ len_hist) {
+    __shared__ unsigned long long cnt_lds[2];
     const int lane = lane_id();
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    // full-length domains and full-length segments all fall in two bins: their
+    // counts are gathered over the whole loop and added once per workgroup
+    unsigned long long full = 0, fullseg = 0;
+    if (threadIdx.x < 2) cnt_lds[threadIdx.x] = 0;
+    __syncthreads();
     for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
         const int64_t lo = series_off[s], n = series_off[s + 1] - series_off[s];
         if (n < 2) continue;
@@ -65,7 +71,6 @@ __global__ void k_fill_domains(const int64_t *__restrict__ series_off, const int
         const int32_t spd = n_segments(D, G);  // segments of a full domain
         const int64_t n_full = (nd - 1) * spd;
         const int32_t nsl = n_segments(last, G);
-        unsigned long long full = 0, fullseg = 0;
         for (int64_t u = lane; u < n_full + nsl; u += kWave) {
             int64_t dom;
             int32_t k, ns, nint_d;
@@ -98,15 +103,20 @@ __global__ void k_fill_domains(const int64_t *__restrict__ series_off, const int
                     atomicAdd(&len_hist[D - x.nint], 1ull);
             }
         }
-        if (len_hist) {
+    }
+    if (len_hist) {
 #pragma unroll
-            for (int m = 1; m < 64; m <<= 1) {
-                full += __shfl_xor(full, m);
-                fullseg += __shfl_xor(fullseg, m);
-            }
-            if (lane == 0 && full) atomicAdd(&len_hist[0], full);
-            if (lane == 0 && fullseg) atomicAdd(&len_hist[D - G], fullseg);
+        for (int m = 1; m < 64; m <<= 1) {
+            full += __shfl_xor(full, m);
+            fullseg += __shfl_xor(fullseg, m);
         }
+        if (lane == 0 && full) atomicAdd(&cnt_lds[0], full);
+        if (lane == 0 && fullseg) atomicAdd(&cnt_lds[1], fullseg);
+    }
+    __syncthreads();
+    if (len_hist && threadIdx.x == 0) {
+        if (cnt_lds[0]) atomicAdd(&len_hist[0], cnt_lds[0]);
+        if (cnt_lds[1]) atomicAdd(&len_hist[D - G], cnt_lds[1]);
     }
 }
 
@@ -656,7 +666,7 @@ int domain_table(const CompressWs &w, const int64_t *series_off, int64_t n_serie
     }
     {
         int64_t fb = (n_series * kWave + 255) / 256;
-        const int64_t cap = (int64_t)device_cu_count() * 16;
+        const int64_t cap = (int64_t)device_cu_count() * 2;
         if (fb > cap) fb = cap;
         if (fb < 1) fb = 1;
         JB_LAUNCH(k_fill_domains, dim3((unsigned)fb), dim3(256), 0, st, series_off, w.dom_off, n_series, D, G, w.doms,
