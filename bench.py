@@ -40,10 +40,11 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes each kernel must move per launch ("Kernels
-# and their rooflines"): n = input points, N = pieces, G = Stage I starting
-# points, k = symbols, nh = reconstructed points.  Only kernels that can be
-# the dominant one are listed.
+# Algorithmic bytes each kernel must move per launch (the data a kernel has
+# to read and write at least, whatever its implementation): n = input
+# points, N = pieces, G = Stage I starting points, k = symbols,
+# nh = reconstructed points.  Only kernels that can be the dominant one are
+# listed.
 def algorithmic_bytes(name: str, n, N, G, k, nh, active_sort_passes, sort_launches):
     if name.startswith("k_compress"):
         return 8.0 * n + 12.0 * N          # read every point once, write (len, inc)

@@ -12,7 +12,7 @@ archive and N(0,1) noise (Sec. 7); the archive is not available here, so the
 generators below stand in for it with random walks, sinusoid mixtures and
 noisy piecewise-linear signals of the same scale.
 
-Workloads (ids follow the order in which they are listed in the design doc):
+Workloads:
 
 1. ``tiny``        16 random walks x 1,000 points, one domain per series,
                    tol = alpha = 0.1.
