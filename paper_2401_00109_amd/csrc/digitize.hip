@@ -411,12 +411,39 @@ __device__ __forceinline__ bool covers(double kq, double xq, double yq, double k
     return in_window & ((dd + ee) <= a2);
 }
 
+// With separated length columns (one length step moves x by more than alpha,
+// the test of k_col_keys) points of different lengths never cover each other
+// (their fl(dx^2) alone exceeds alpha^2) and points of one length have
+// bit-identical x, so the test is x equality, the key window and
+// fl(dy^2) <= alpha^2 (fl(0 + dy^2) = fl(dy^2)): the same decisions with
+// fewer FP64 operations.
+template <bool Col>
+__device__ __forceinline__ bool covers_t(double kq, double xq, double yq, double kp, double xp, double yp, double alpha,
+                                         double a2) {
+    if constexpr (Col) {
+        const bool same = __double_as_longlong(xq) == __double_as_longlong(xp);
+        const bool in_window = kq - kp <= alpha;
+        const double dy = yq - yp;
+        const double ee = dy * dy;
+        return same & in_window & (ee <= a2);
+    } else {
+        return covers(kq, xq, yq, kp, xp, yp, alpha, a2);
+    }
+}
+
+// whether the length columns are separated (see k_col_keys)
+__device__ __forceinline__ bool columns_separated(const DigState *ds, double scl, double a2) {
+    const double step = scl / ds->sigma_len;
+    return step * step > a2 * (1.0 + 1e-9);
+}
+
 // Runs the greedy over positions [from, to) with the active list A as the
 // state before `from`.  Owners are written to lab/flag when `write`.
 // Points are staged kStage batches at a time (all loads of a chunk in flight
 // together); within a batch each lane first tests its point against the
 // active starts, oldest first, and the points no active start covers are
 // then resolved among themselves in lane order (one step per new start).
+template <bool Col>
 __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__restrict__ key,
                            const double *__restrict__ x, const double *__restrict__ y, double alpha, double a2,
                            bool write, int32_t *__restrict__ lab, uint32_t *__restrict__ flag,
@@ -455,7 +482,7 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                     for (; i < fc; ++i) {
                         if (ballot(open) == 0ull) break;
                         const int32_t pp = __hip_atomic_load(&A.glist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (open && covers(kq, xq, yq, key[pp], x[pp], y[pp], alpha, a2)) {
+                        if (open && covers_t<Col>(kq, xq, yq, key[pp], x[pp], y[pp], alpha, a2)) {
                             owner = pp;
                             open = false;
                         }
@@ -480,7 +507,7 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                         bool hit[kGroup];
 #pragma unroll
                         for (int u = 0; u < kGroup; ++u)
-                            hit[u] = (i + u < A.tail) & covers(kq, xq, yq, gk[u], gx[u], gy[u], alpha, a2);
+                            hit[u] = (i + u < A.tail) & covers_t<Col>(kq, xq, yq, gk[u], gx[u], gy[u], alpha, a2);
 #pragma unroll
                         for (int u = 0; u < kGroup; ++u) {
                             if (open && hit[u]) {
@@ -500,7 +527,7 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                     if (lane == l) {
                         owner = pl;
                         open = false;
-                    } else if (open && lane > l && covers(kq, xq, yq, kl, xl, yl, alpha, a2)) {
+                    } else if (open && lane > l && covers_t<Col>(kq, xq, yq, kl, xl, yl, alpha, a2)) {
                         owner = pl;
                         open = false;
                     }
@@ -538,6 +565,7 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
 __global__ __launch_bounds__(1024) void k_stage1(const int64_t *__restrict__ cuts, int64_t nblk_max,
                                                  const double *__restrict__ sk, const double *__restrict__ sx,
                                                  const double *__restrict__ sy, double alpha, double a2,
+                                                 const DigState *ds, double scl,
                                                  int32_t *__restrict__ glist, int32_t *__restrict__ lab,
                                                  uint32_t *__restrict__ flag, int32_t *__restrict__ start_blk) {
     extern __shared__ ActLds act_lds[];
@@ -547,7 +575,10 @@ __global__ __launch_bounds__(1024) void k_stage1(const int64_t *__restrict__ cut
     const int64_t lo = cuts[blk], hi = cuts[blk + 1];
     if (lo >= hi) return;
     Active A{&act_lds[wave], glist + lo, 0, 0};
-    pull_range(lo, hi, A, sk, sx, sy, alpha, a2, true, lab, flag, start_blk, (int32_t)blk);
+    if (columns_separated(ds, scl, a2))
+        pull_range<true>(lo, hi, A, sk, sx, sy, alpha, a2, true, lab, flag, start_blk, (int32_t)blk);
+    else
+        pull_range<false>(lo, hi, A, sk, sx, sy, alpha, a2, true, lab, flag, start_blk, (int32_t)blk);
 }
 
 // Stage II runs on independent groups of starting points.  Two starting
@@ -624,17 +655,22 @@ __global__ __launch_bounds__(256) void k_col_greedy(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ gstart, const int32_t *__restrict__ ord,
                                                     const double *__restrict__ ck, const double *__restrict__ cx,
                                                     const double *__restrict__ cy, double alpha, double a2,
+                                                    const DigState *ds, double scl,
                                                     int32_t *__restrict__ glist, int32_t *__restrict__ own,
                                                     uint32_t *__restrict__ oflag, int32_t *__restrict__ glab,
                                                     uint32_t *__restrict__ gflag) {
     extern __shared__ ActLds act_lds[];
     const int wave = threadIdx.x / kWave;
     const int64_t ng = *n_groups_p;
+    const bool sep = columns_separated(ds, scl, a2);
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave; gi < ng; gi += waves) {
         const int64_t lo = gstart[gi], hi = gstart[gi + 1];
         Active A{&act_lds[wave], glist + lo, 0, 0};
-        pull_range(lo, hi, A, ck, cx, cy, alpha, a2, true, own, oflag);
+        if (sep)
+            pull_range<true>(lo, hi, A, ck, cx, cy, alpha, a2, true, own, oflag);
+        else
+            pull_range<false>(lo, hi, A, ck, cx, cy, alpha, a2, true, own, oflag);
         __threadfence();  // owners written by other lanes are read back below
         for (int64_t j = lo + lane_id(); j < hi; j += kWave) {
             const int32_t g = ord[j];
@@ -1323,7 +1359,7 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     JB_LAUNCH_CHECK();
     const size_t lds = (size_t)s1w * sizeof(ActLds);
     JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk, w.sk,
-              w.sx, w.sy, alpha, a2, w.glist, w.lab, w.flag, w.sblk);
+              w.sx, w.sy, alpha, a2, w.ds, scl, w.glist, w.lab, w.flag, w.sblk);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.flag, w.sidx, n_live, N, w.scan_ws, st);
     if (rc) return rc;
@@ -1359,7 +1395,8 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     JB_LAUNCH(k_col_groups, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.cut, w.cgid, w.gstart, w.n_groups);
     JB_LAUNCH_CHECK();
     JB_LAUNCH(k_col_greedy, dim3(grid_for(N * kWave / 4 + 1, 32)), dim3(4 * kWave), 4 * sizeof(ActLds), st,
-              w.n_groups, w.gstart, w.ord, w.ck, w.cx, w.cy, alpha, a2, w.glist, w.own, w.oflag, w.glab, w.gflag);
+              w.n_groups, w.gstart, w.ord, w.ck, w.cx, w.cy, alpha, a2, w.ds, scl, w.glist, w.own, w.oflag, w.glab,
+              w.gflag);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
@@ -1428,7 +1465,7 @@ extern "C" int jabba_aggregate_points(const double *x, const double *y, const in
     JB_LAUNCH_CHECK();
     const size_t lds = (size_t)s1w * sizeof(ActLds);
     JB_LAUNCH(k_stage1, dim3((unsigned)((nblk + s1w - 1) / s1w)), dim3(s1w * kWave), lds, st, w.cuts, nblk, w.sk,
-              w.sx, w.sy, alpha, a2, w.glist, w.lab, w.flag, w.sblk);
+              w.sx, w.sy, alpha, a2, w.ds, 0.0, w.glist, w.lab, w.flag, w.sblk);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.flag, w.sidx, n_live, N, w.scan_ws, st);
     if (rc) return rc;
@@ -1455,7 +1492,8 @@ extern "C" int jabba_aggregate_points(const double *x, const double *y, const in
     JB_LAUNCH(k_col_groups, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.cut, w.cgid, w.gstart, w.n_groups);
     JB_LAUNCH_CHECK();
     JB_LAUNCH(k_col_greedy, dim3(grid_for(N * kWave / 4 + 1, 32)), dim3(4 * kWave), 4 * sizeof(ActLds), st,
-              w.n_groups, w.gstart, w.ord, w.ck, w.cx, w.cy, alpha, a2, w.glist, w.own, w.oflag, w.glab, w.gflag);
+              w.n_groups, w.gstart, w.ord, w.ck, w.cx, w.cy, alpha, a2, w.ds, 0.0, w.glist, w.own, w.oflag, w.glab,
+              w.gflag);
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
