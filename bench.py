@@ -89,6 +89,8 @@ def main() -> int:
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain 1 GiB copy kernel (for rocprofv3 counter scaling)")
     ap.add_argument("--tuning", default=None, help="JSON dict of jabba_tuning fields")
+    ap.add_argument("--pipeline", type=int, default=0,
+                    help="buffer sets in flight (one stream each); 0 = 2 up to 2e8 points, else 1")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -145,15 +147,61 @@ def main() -> int:
         sz.compress(v, so)
         sz.digitize()
 
-    def step_all():
-        step_sym()
-        J.encode(full.len, full.inc, full.n_pieces, N, resident, symbols=enc)
-        rec.run(sz.symbols, sz.dictionary)
+    # One step = compress, encode against the resident dictionary, digitize,
+    # reconstruct, for one batch.  Consecutive batches alternate between
+    # buffer sets, one stream each, so batch i+1's compression (a few
+    # wavefronts per compute unit) overlaps batch i's digitization and
+    # reconstruction; every batch still does all of its work.
+    n_sets = args.pipeline if args.pipeline > 0 else (2 if w.n_points <= 200_000_000 else 1)
+
+    def make_set(sz_, full_, enc_, rec_):
+        return {"sz": sz_, "full": full_, "enc": enc_, "rec": rec_, "st": torch.cuda.Stream(device=dev),
+                "ews": J.api._ws(J.api.encode_workspace_bytes(resident.capacity), dev)}
+
+    sets = [make_set(sz, full, enc, rec)]
+
+    def step_set(S):
+        st = S["st"]
+        S["sz"].compress(v, so, stream=st)
+        J.encode(S["full"].len, S["full"].inc, S["full"].n_pieces, N, resident, symbols=S["enc"],
+                 workspace=S["ews"], stream=st)
+        S["sz"].digitize(stream=st)
+        S["rec"].run(S["sz"].symbols, S["sz"].dictionary, stream=st)
+
+    def fork():
+        ev = torch.cuda.Event()
+        ev.record()
+        for S in sets:
+            S["st"].wait_event(ev)
+
+    def join():
+        for S in sets:
+            ev = torch.cuda.Event()
+            ev.record(S["st"])
+            torch.cuda.current_stream().wait_event(ev)
+
+    def run_steps(n, pipelined=True):
+        fork()
+        for i in range(n):
+            step_set(sets[i % len(sets)] if pipelined else sets[0])
+        join()
+
 
     step_sym()
     rec.size(sz.symbols, sz.dictionary)
-    for _ in range(max(args.warmup, 1)):
-        step_all()
+    for _ in range(1, n_sets):
+        sz_b = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B, max_pieces=max(N, 1),
+                            capacity=max(N, 1), tuning=tuning)
+        full_b = J.Pieces(torch.empty(max(w.n_points, 1), dtype=torch.int32, device=dev),
+                          torch.empty(max(w.n_points, 1), dtype=torch.float64, device=dev),
+                          sz_b.pieces.piece_off, sz_b.pieces.n_pieces, max(w.n_points, 1))
+        sz_b.pieces = full_b
+        rec_b = J.Reconstructor(full_b.piece_off, so, t0, v)
+        sz_b.compress(v, so)
+        sz_b.digitize()
+        rec_b.size(sz_b.symbols, sz_b.dictionary)
+        sets.append(make_set(sz_b, full_b, torch.empty(max(w.n_points, 1), dtype=torch.int32, device=dev), rec_b))
+    run_steps(max(args.warmup, 1) * len(sets))
     torch.cuda.synchronize()
     st = sz.status()
     if st != (0, 0):
@@ -170,13 +218,22 @@ def main() -> int:
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
-    for _ in range(args.steps):
-        step_all()
+    run_steps(args.steps)
     ev1.record()
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / args.steps
     value = w.n_points / (ms_step / 1e3)
-    log(f"full step {ms_step:.3f} ms -> {value:.4e} points/s")
+    for S in sets[1:]:
+        assert torch.equal(S["sz"].symbols[:N], sz.symbols[:N]) and torch.equal(S["enc"][:N], enc[:N]), \
+            "buffer sets disagree"
+        assert S["sz"].status() == (0, 0)
+    ev0.record()
+    run_steps(args.steps, pipelined=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_serial = ev0.elapsed_time(ev1) / args.steps
+    log(f"full step {ms_step:.3f} ms with {len(sets)} buffer set(s) in flight -> {value:.4e} points/s "
+        f"(one batch at a time: {ms_serial:.3f} ms)")
 
     # symbolization only (compress + digitize), eager and as one graph replay
     ev0.record()
@@ -204,27 +261,43 @@ def main() -> int:
     log(f"symbolize {ms_sym:.3f} ms eager, graph {ms_graph if ms_graph is None else round(ms_graph, 3)} ms")
 
     # ---------------------------------------------------------------- per-kernel events
-    J.timing_enable(True)
-    for _ in range(args.steps):
-        step_all()
-    torch.cuda.synchronize()
-    rep = J.timing_report()
-    J.timing_enable(False)
-    per_step = {n: (ms / args.steps, cnt / args.steps) for n, (ms, cnt) in rep.items()}
-    n_hat = int(rec.out_off[-1].item())
-    dom_name = max(rep, key=lambda n: rep[n][0])
-    dom_ms, dom_launches = rep[dom_name]
-    sort_launches = rep.get("k_onesweep", (0, 1))[1] / args.steps
-    alg = algorithmic_bytes(dom_name, w.n_points, N, G, k, n_hat, active_passes, sort_launches)
-    roofline = None
-    if alg is not None and dom_launches > 0:
-        avg_ms = dom_ms / dom_launches
+    # The roofline is taken one batch at a time, so a kernel's duration is its
+    # own (with batches in flight a kernel shares the device with the other
+    # batch's kernels; those durations are reported beside it).
+    def kernel_times(pipelined):
+        J.timing_enable(True)
+        run_steps(args.steps, pipelined=pipelined)
+        torch.cuda.synchronize()
+        rep = J.timing_report()
+        J.timing_enable(False)
+        return rep
+
+    def roofline_of(rep):
+        name = max(rep, key=lambda n: rep[n][0])
+        ms, launches = rep[name]
+        sort_launches = rep.get("k_onesweep", (0, 1))[1] / args.steps
+        alg = algorithmic_bytes(name, w.n_points, N, G, k, n_hat, active_passes, sort_launches)
+        if alg is None or launches <= 0:
+            return None
+        avg_ms = ms / launches
         achieved = alg / (avg_ms / 1e3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(dom_name),
-                    "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(avg_ms, 5)}
+        return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(name),
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(avg_ms, 5)}
+
+    n_hat = int(rec.out_off[-1].item())
+    rep = kernel_times(False)
+    per_step = {n: (ms / args.steps, cnt / args.steps) for n, (ms, cnt) in rep.items()}
+    roofline = roofline_of(rep)
     top = sorted(per_step.items(), key=lambda kv: -kv[1][0])[:12]
-    log("per-step kernel time: " + ", ".join(f"{n} {ms:.3f}ms" for n, (ms, _) in top))
+    log("per-step kernel time (one batch at a time): " + ", ".join(f"{n} {ms:.3f}ms" for n, (ms, _) in top))
+    in_flight = None
+    if len(sets) > 1:
+        rf = roofline_of(kernel_times(True))
+        if rf is not None:
+            in_flight = {"kernel": rf["kernel"], "avg_launch_ms": rf["avg_launch_ms"], "achieved": rf["achieved"],
+                         "frac": rf["frac"]}
+            log(f"with {len(sets)} batches in flight {rf['kernel']} averages {rf['avg_launch_ms']:.4f} ms per launch")
 
     # ---------------------------------------------------------------- batched vs plain launches
     plain = None
@@ -291,6 +364,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_one_batch_at_a_time": round(ms_serial, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -301,12 +375,14 @@ def main() -> int:
                                f"tol={w.tol}, alpha={w.alpha}, B={w.B}",
                    "points": w.n_points, "pieces": N, "symbols": k, "starting_points": G,
                    "stage2_groups": groups2,
-                   "step": "compress+digitize+encode(resident k=%d)+reconstruct" % resident.size()},
+                   "step": "compress+digitize+encode(resident k=%d)+reconstruct" % resident.size(),
+                   "batches_in_flight": len(sets)},
         "symbolize_points_per_s": round(w.n_points / (ms_sym / 1e3), 1),
         "symbolize_ms": round(ms_sym, 4),
         "symbolize_graph_ms": None if ms_graph is None else round(ms_graph, 4),
         "kernel_ms_per_step": {n: round(ms, 4) for n, (ms, _) in top},
         "roofline": roofline,
+        "dominant_kernel_with_batches_in_flight": in_flight,
         "batched_vs_plain": plain,
         "cpu_baseline": cpu,
         "reconstruction_mse": rec.mse(),

@@ -1,9 +1,8 @@
 // Stable LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
 //
-// Used for the global sorting index of Sec. 5: keys are the bit patterns of
-// non-negative binary64 sort keys (their unsigned order is the numeric
-// order) and values are canonical piece indices, so equal keys keep the
-// canonical order.
+// Used for the global sorting index of Sec. 5: keys are unsigned integers in
+// the order of the binary64 sort keys and values are canonical piece
+// indices, so equal keys keep the canonical order.
 //
 // One kernel per digit ("one sweep"): the global histograms of all eight
 // digits are taken once, up front; a pass takes tiles in ticket order, counts
