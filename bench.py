@@ -45,11 +45,14 @@ def log(msg: str) -> None:
 # points, N = pieces, G = Stage I starting points, k = symbols,
 # nh = reconstructed points.  Only kernels that can be the dominant one are
 # listed.
-def algorithmic_bytes(name: str, n, N, G, k, nh, active_sort_passes, sort_launches):
+def algorithmic_bytes(name: str, n, N, G, k, nh, sort_bytes, sort_launches):
     if name.startswith("k_compress"):
         return 8.0 * n + 12.0 * N          # read every point once, write (len, inc)
-    if name == "k_onesweep":              # 12 B in + 12 B out per pair, active passes only
-        return 24.0 * N * active_sort_passes / max(sort_launches, 1)
+    if name == "k_onesweep":
+        # per pair, summed over the active passes: key (8 B, or 4 B once the
+        # digits left fit) and value in; key and value out, the value alone
+        # in the last pass
+        return float(sort_bytes) * N / max(sort_launches, 1)
     if name == "k_stage1":
         return 32.0 * N + 8.0 * G          # sorted key, x, y in; label, flag out; start tags, list
     if name == "k_block_sums":
@@ -57,7 +60,7 @@ def algorithmic_bytes(name: str, n, N, G, k, nh, active_sort_passes, sort_launch
     if name == "k_col_greedy":
         return 56.0 * G
     if name == "k_gather":
-        return 68.0 * N                    # perm, key, random 16-byte record in; 5 sorted arrays out
+        return 60.0 * N                    # perm, random 16-byte record in; 6 sorted arrays out
     if name == "k_key":
         return 40.0 * N                    # len, inc in; key, index, record out
     if name == "k_encode" or name.startswith("k_encode<"):
@@ -209,9 +212,9 @@ def main() -> int:
         return 1
     k = sz.dictionary.size()
     stats = sz.stats()
-    G, active_passes = stats["G"], stats["sort_passes"]
+    G, active_passes, sort_bytes = stats["G"], stats["sort_passes"], stats["sort_bytes"]
     groups2 = stats["stage2_groups"]
-    log(f"N={N} pieces, G={G} starting points, k={k} symbols, {active_passes} radix passes, "
+    log(f"N={N} pieces, G={G} starting points, k={k} symbols, {active_passes} radix passes ({sort_bytes} B per piece), "
         f"{groups2} Stage II groups, reconstruction MSE={rec.mse():.4e}")
 
     # ---------------------------------------------------------------- timed region
@@ -276,7 +279,7 @@ def main() -> int:
         name = max(rep, key=lambda n: rep[n][0])
         ms, launches = rep[name]
         sort_launches = rep.get("k_onesweep", (0, 1))[1] / args.steps
-        alg = algorithmic_bytes(name, w.n_points, N, G, k, n_hat, active_passes, sort_launches)
+        alg = algorithmic_bytes(name, w.n_points, N, G, k, n_hat, sort_bytes, sort_launches)
         if alg is None or launches <= 0:
             return None
         avg_ms = ms / launches

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define JABBA_ABI_VERSION 1
+#define JABBA_ABI_VERSION 2
 
 enum jabba_status {
     JABBA_OK = 0,
@@ -291,7 +291,9 @@ int jabba_axis_tolerances(double alpha_len, double alpha_inc, double scl_in, dou
  * and B): stats[0] = N pieces, stats[1] = G Stage I starting points,
  * stats[2] = k symbols, stats[3] = radix passes that moved data (digits that
  * are equal in every key are skipped), stats[4] = number of independent groups
- * Stage II ran on.  stats holds 5 entries.
+ * Stage II ran on, stats[5] = bytes per piece those radix passes read and
+ * wrote together (keys narrow to 32 bits once the digits left to sort fit).
+ * stats holds 6 entries.
  * Synchronises `stream`.
  */
 int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream, int64_t *stats);

@@ -165,11 +165,13 @@ class Dictionary:
 
 
 def digitize_stats(workspace: torch.Tensor, max_pieces: int, B: int, stream=None) -> dict:
-    """N, G (Stage I starting points), k and active radix passes of the last digitize on this workspace."""
-    arr = (C.c_int64 * 5)()
+    """N, G (Stage I starting points), k, active radix passes, Stage II groups and the
+    bytes per piece the radix passes moved, for the last digitize on this workspace."""
+    arr = (C.c_int64 * 6)()
     L.check(L.lib().jabba_digitize_stats(_p(workspace), int(max_pieces), int(B), _stream(stream), arr),
             "jabba_digitize_stats")
-    return {"N": arr[0], "G": arr[1], "k": arr[2], "sort_passes": arr[3], "stage2_groups": arr[4]}
+    return {"N": arr[0], "G": arr[1], "k": arr[2], "sort_passes": arr[3], "stage2_groups": arr[4],
+            "sort_bytes": arr[5]}
 
 
 def workspace_status(ws: torch.Tensor, stream=None) -> int:

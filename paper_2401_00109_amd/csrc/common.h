@@ -188,12 +188,20 @@ struct SortBuffers {
 size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b);
 // Resets the control words and the global digit histograms.
 int radix_sort_init(const SortBuffers &b, hipStream_t st);
+// ctl[kSortCtlMode + d]: the key widths pass d of the last sort moved.
+constexpr int kSortCtlMode = 40;
+constexpr int kSortModeIn32 = 1;    // read 32-bit keys
+constexpr int kSortModeOut32 = 2;   // wrote 32-bit keys
+constexpr int kSortModeNoKeys = 4;  // wrote no keys (order only)
+
 // Global histograms of the eight digits of keys[0] (after the keys are written).
 int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);
 // Sorts n (device count) pairs held in keys[0]/vals[0]; the result is in
-// keys[ctl[0]], vals[ctl[0]] (read on device by consumers).
+// keys[ctl[0]], vals[ctl[0]] (read on device by consumers).  With keep_keys
+// false only vals[ctl[0]] holds the result (the sorted order); the key
+// buffers then hold intermediate, narrowed keys.
 // `tag` suffixes the timing names of the pass kernels ("" for the main sort).
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st,
-                     const char *tag = "");
+                     const char *tag = "", bool keep_keys = true);
 
 }  // namespace jabba

@@ -39,6 +39,7 @@ struct DigState {
     double axis[2];   // unit principal axis (PCA key)
     int64_t n;  // live piece count (clamped)
     int64_t sort_passes;  // radix passes of the main sort that moved data
+    int64_t sort_bytes;   // bytes per pair those passes read and wrote
 };
 
 __global__ void k_dig_prepare(DigState *ds, const int64_t *n_dev, int64_t n_max) {
@@ -260,6 +261,23 @@ struct __align__(16) PieceRec {
     int32_t pad;
 };
 
+// Sort key of one scaled piece (Sec. 5): its norm, or its projection on the
+// principal axis (ux, uy); -0 is taken as +0.  The key kernel and the gather
+// both evaluate it here, so the sorted keys the gather writes are the keys
+// the sort ordered.
+template <int Key>
+__device__ __forceinline__ double sort_key(Scaled s, double ux, double uy) {
+    double k;
+    if (Key == kKeyPca) {
+        const double px = ux * s.x;
+        const double py = uy * s.y;
+        k = px + py;
+    } else {
+        k = piece_key(s);
+    }
+    return k == 0.0 ? 0.0 : k;
+}
+
 template <int Key>
 __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict__ inc, const DigState *ds, double scl,
                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, PieceRec *__restrict__ rec) {
@@ -270,15 +288,7 @@ __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict_
         const int32_t l = len[i];
         const double ic = inc[i];
         const Scaled s = scale_piece(l, ic, scl, sl, si);
-        double k;
-        if (Key == kKeyPca) {
-            const double px = ux * s.x;
-            const double py = uy * s.y;
-            k = px + py;
-        } else {
-            k = piece_key(s);
-        }
-        keys[i] = key_bits(k);
+        keys[i] = key_bits(sort_key<Key>(s, ux, uy));
         vals[i] = (uint32_t)i;
         PieceRec r;
         r.inc = ic;
@@ -288,19 +298,28 @@ __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict_
     }
 }
 
-__global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds,
-                         double scl, const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+// Pieces in sorted order.  The main sort leaves the order only (no sorted
+// keys), so the key is evaluated again from the piece.
+template <int Key>
+__global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds, double scl,
                          const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
                          double *__restrict__ sk, double *__restrict__ sx, double *__restrict__ sy,
                          int32_t *__restrict__ slen, double *__restrict__ sinc, uint32_t *__restrict__ perm) {
     const int64_t n = ds->n;
     const double sl = ds->sigma_len, si = ds->sigma_inc;
-    const uint64_t *ks = ctl[0] ? k1 : k0;
+    const double ux = Key == kKeyPca ? ds->axis[0] : 0.0, uy = Key == kKeyPca ? ds->axis[1] : 0.0;
     const uint32_t *vs = ctl[0] ? v1 : v0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int64_t act = 0;
-        for (int d = 0; d < 8; ++d) act += ctl[1 + d] ? 0 : 1;
+        int64_t act = 0, bytes = 0;
+        for (int d = 0; d < 8; ++d) {
+            if (ctl[1 + d]) continue;
+            const int mode = ctl[kSortCtlMode + d];
+            act += 1;
+            bytes += ((mode & kSortModeIn32) ? 4 : 8) + 4 +
+                     ((mode & kSortModeNoKeys) ? 0 : (mode & kSortModeOut32) ? 4 : 8) + 4;
+        }
         ds->sort_passes = act;
+        ds->sort_bytes = bytes;
         if (ctl[32]) set_status(ds->status, kStInternal);  // a radix look-back wait ran out
     }
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -309,7 +328,7 @@ __global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds,
         const int32_t l = r.len;
         const double ic = r.inc;
         const Scaled s = scale_piece(l, ic, scl, sl, si);
-        sk[p] = key_of_bits(ks[p]);
+        sk[p] = sort_key<Key>(s, ux, uy);
         sx[p] = s.x;
         sy[p] = s.y;
         slen[p] = l;
@@ -953,6 +972,7 @@ __global__ void k_pts_gather(const PointRec *__restrict__ rec, DigState *ds, con
         int64_t act = 0;
         for (int d = 0; d < 8; ++d) act += ctl[1 + d] ? 0 : 1;
         ds->sort_passes = act;
+        ds->sort_bytes = 24 * act;  // 64-bit keys and 32-bit values in and out
         if (ctl[32]) set_status(ds->status, kStInternal);
     }
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -1348,10 +1368,14 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     const int64_t *n_live = &w.ds->n;
     rc = radix_global_hist(w.sb, n_live, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, n_live, N, st);
+    rc = radix_sort_pairs(w.sb, n_live, N, st, "", /*keep_keys=*/false);
     if (rc) return rc;
-    JB_LAUNCH(k_gather, dim3(grid_for(N)), dim3(256), 0, st, w.rec, w.ds, scl, w.sb.keys[0],
-                       w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
+    if (key_kind == kKeyPca)
+        JB_LAUNCH_NAMED("k_gather_pca", (k_gather<kKeyPca>), dim3(grid_for(N)), dim3(256), 0, st, w.rec, w.ds, scl,
+                        w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
+    else
+        JB_LAUNCH_NAMED("k_gather", (k_gather<kKeyNorm>), dim3(grid_for(N)), dim3(256), 0, st, w.rec, w.ds, scl,
+                        w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
     JB_LAUNCH_CHECK();
 
     // Stage I: blocks of B sorted pieces, one wavefront each
@@ -1570,6 +1594,7 @@ extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, i
     int64_t ng = 0;
     JB_HIP(hipMemcpy(&ng, w.n_groups, sizeof(int64_t), hipMemcpyDeviceToHost));
     stats[4] = ng;
+    stats[5] = ds.sort_bytes;
     return JABBA_OK;
 }
 

@@ -17,6 +17,11 @@
 // same for every key is skipped; the decision and the buffer parity of every
 // pass are taken on the device from the global histograms, so no host
 // read-back is needed and the sort can be captured in a HIP graph.
+//
+// A sort whose caller needs only the order (not the sorted keys) carries
+// less: once the digits not yet sorted fit in 32 bits, the passes read and
+// write 32-bit keys (key - kmin shifted past the sorted digits), and the last
+// pass writes the values alone.
 #include "common.h"
 
 namespace jabba {
@@ -32,6 +37,11 @@ constexpr int kCtlFinal = 0;   // buffer holding the sorted order after all pass
 constexpr int kCtlSkip = 1;    // [1..8]: digit d is the same for every key
 constexpr int kCtlSrc = 9;     // [9..16]: buffer pass d reads
 constexpr int kCtlError = 32;  // a look-back wait ran out (never expected)
+constexpr int kCtlMode = kSortCtlMode;  // [40..47]: key widths of pass d
+constexpr int kCtlBase = 48;            // bit offset of the 32-bit keys inside key - kmin
+constexpr int kModeIn32 = kSortModeIn32;
+constexpr int kModeOut32 = kSortModeOut32;
+constexpr int kModeNoKeys = kSortModeNoKeys;
 
 // status word: [63:56] pass tag, [55:54] flag, [31:0] count
 constexpr uint64_t kFlagAgg = 1ull << 54;
@@ -131,9 +141,11 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
 }
 
 // Per digit: skip flag, bucket bases (exclusive scan of the global
-// histogram), and the buffer each pass reads.  One workgroup of 256.
+// histogram), the buffer each pass reads and the key widths it moves.  One
+// workgroup of 256.
 __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ ghist, const int64_t *n_dev,
-                                                   int64_t n_max, int32_t *ctl, uint32_t *__restrict__ gbase) {
+                                                   int64_t n_max, int keep_keys, int32_t *ctl,
+                                                   uint32_t *__restrict__ gbase) {
     __shared__ uint32_t s_wave[kThreads / kWave];
     __shared__ int s_full;
     const int64_t n = live(n_dev, n_max);
@@ -152,7 +164,33 @@ __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ 
         active += skip ? 0 : 1;
         __syncthreads();
     }
-    if (threadIdx.x == 0) ctl[kCtlFinal] = active & 1;
+    if (threadIdx.x == 0) {
+        ctl[kCtlFinal] = active & 1;
+        // key - kmin is 0 on the smallest key, so a skipped digit is 0 in
+        // every key; digits above the highest active one can be dropped
+        int top = -1;
+        for (int d = 0; d < 8; ++d)
+            if (!ctl[kCtlSkip + d]) top = d;
+        bool narrow = false;
+        int base = 0;
+        for (int d = 0; d < 8; ++d) {
+            int mode = 0;
+            if (!ctl[kCtlSkip + d] && !keep_keys) {
+                mode = narrow ? kModeIn32 : 0;
+                if (d == top) {
+                    mode |= kModeNoKeys;
+                } else if (narrow) {
+                    mode |= kModeOut32;
+                } else if (top - d <= 4) {  // digits d+1..top fit in 32 bits
+                    mode |= kModeOut32;
+                    narrow = true;
+                    base = 8 * (d + 1);
+                }
+            }
+            ctl[kCtlMode + d] = mode;
+        }
+        ctl[kCtlBase] = base;
+    }
 }
 
 // Exclusive scan over the NT threads of a block (one value per thread).
@@ -175,7 +213,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wave
 }
 
 // A pass over one tile of kTileN pairs with kSweepThreads threads: threads
-// below 256 own one digit each (histogram, look-back, bucket bases).
+// below 256 own one digit each (histogram, look-back, bucket bases).  The
+// per-wave digit counts and the tile histogram share LDS with the staged
+// keys (they are dead before the tile is staged).
 constexpr int kSweepThreads = 512;
 constexpr int kSweepRounds = kTileN / kSweepThreads;
 
@@ -190,13 +230,21 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
     if (ctl[kCtlSkip + pass]) return;
     constexpr int kWaves = kSweepThreads / kWave;
     constexpr int kPerWave = kTileN / kWaves;  // contiguous slice of the tile per wavefront
-    __shared__ uint64_t s_key[kTileN];
+    __shared__ union {
+        uint64_t key[kTileN];  // the ranked tile, staged for the write-out
+        struct {
+            uint32_t wrun[kWaves][256];  // per-wave count, then per-wave offset, per digit
+            uint32_t hist[256];
+        } rank;
+    } s_u;
+    static_assert(sizeof(s_u.rank) <= sizeof(s_u.key), "ranking state must fit the staging buffer");
     __shared__ uint32_t s_val[kTileN];
-    __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_lo[256];            // local start per digit
-    __shared__ uint32_t s_go[256];            // destination start per digit
-    __shared__ uint32_t s_wrun[kWaves][256];  // per-wave count, then per-wave offset, per digit
+    __shared__ uint32_t s_lo[256];  // local start per digit
+    __shared__ uint32_t s_go[256];  // destination start per digit
     __shared__ uint32_t s_wave[kWaves];
+    uint32_t *const s_hist = s_u.rank.hist;
+    uint32_t (*const s_wrun)[256] = s_u.rank.wrun;
+    uint64_t *const s_key = s_u.key;
     __shared__ int64_t s_tile;
     const int tid = threadIdx.x;
     const int w = tid / kWave;
@@ -219,7 +267,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
     uint32_t *vd = src1 ? v0 : v1;
     const int m = (int)(n - base < kTileN ? n - base : kTileN);
     const uint64_t kbase = *kmin;
-    auto digit = [&](uint64_t key) -> uint32_t { return (uint32_t)((key - kbase) >> shift) & 255u; };
+    const int mode = ctl[kCtlMode + pass];
+    const bool in32 = (mode & kModeIn32) != 0;
+    const int nshift = ctl[kCtlBase];  // 32-bit keys hold key - kmin from this bit up
+    // 64-bit keys are held as read; 32-bit keys are zero-extended
+    auto digit = [&](uint64_t key) -> uint32_t {
+        return in32 ? (uint32_t)(key >> (shift - nshift)) & 255u : (uint32_t)((key - kbase) >> shift) & 255u;
+    };
+    const uint32_t *ks32 = reinterpret_cast<const uint32_t *>(ks);
 
     // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
     // (wave, round, lane) order is index order; all loads in flight at once
@@ -228,12 +283,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
 #pragma unroll
     for (int r = 0; r < kSweepRounds; ++r) {
         const int li = w * kPerWave + r * kWave + lane;
-        kr[r] = li < m ? ks[base + li] : 0ull;
+        kr[r] = li < m ? (in32 ? (uint64_t)ks32[base + li] : ks[base + li]) : 0ull;
         vr[r] = li < m ? vs[base + li] : 0u;
     }
+    // per element: its digit, later (wave-local rank << 8 | digit), later its
+    // slot in the ranked tile (one register per element across the look-back)
+    uint32_t dp[kSweepRounds];
 #pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r)
-        if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[digit(kr[r])], 1u);
+    for (int r = 0; r < kSweepRounds; ++r) {
+        dp[r] = digit(kr[r]);
+        if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[dp[r]], 1u);
+    }
     __syncthreads();
     const uint32_t cnt = digit_owner ? s_hist[tid] : 0u;
 
@@ -245,12 +305,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
 
     // wave-local ranking in index order: peers with the same digit by eight
     // ballots, a running count per digit in this wave's LDS row
-    uint32_t wpos[kSweepRounds];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < kSweepRounds; ++r) {
         const bool ok = w * kPerWave + r * kWave + lane < m;
-        const uint32_t dg = digit(kr[r]);
+        const uint32_t dg = dp[r];
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -260,7 +319,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
         const uint32_t run = s_wrun[w][dg];
-        wpos[r] = run + rank;
+        dp[r] |= (run + rank) << 8;
         if (ok && rank == 0) s_wrun[w][dg] = run + (uint32_t)__popcll(peers);
     }
 
@@ -269,7 +328,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
     // first until a prefix is found, waiting only on words not yet published.
     uint64_t excl = 0;
     if (digit_owner && tile > 0) {
-        constexpr int kWindow = 8;
+        constexpr int kWindow = 4;
         const uint64_t ready_tag = (uint64_t)(pass + 1);
         int64_t t = tile - 1;
         int spins = 0;
@@ -320,11 +379,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSweepRounds; ++r) {
+        const uint32_t dg = dp[r] & 255u;
+        dp[r] = (dp[r] >> 8) + s_lo[dg] + s_wrun[w][dg];  // slot in the ranked tile
+    }
+    __syncthreads();  // the counts are read; their storage becomes the staged keys
+#pragma unroll
+    for (int r = 0; r < kSweepRounds; ++r) {
         if (w * kPerWave + r * kWave + lane < m) {
-            const uint32_t dg = digit(kr[r]);
-            const uint32_t lp = s_lo[dg] + s_wrun[w][dg] + wpos[r];
-            s_key[lp] = kr[r];
-            s_val[lp] = vr[r];
+            s_key[dp[r]] = kr[r];
+            s_val[dp[r]] = vr[r];
         }
     }
     __syncthreads();
@@ -336,7 +399,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
             const uint64_t key = s_key[j];
             const uint32_t dg = digit(key);
             const uint32_t pos = s_go[dg] + ((uint32_t)j - s_lo[dg]);
-            kd[pos] = key;
+            if (mode & kModeOut32)
+                reinterpret_cast<uint32_t *>(kd)[pos] = in32 ? (uint32_t)key : (uint32_t)((key - kbase) >> nshift);
+            else if (!(mode & kModeNoKeys))
+                kd[pos] = key;
             vd[pos] = s_val[j];
         }
     }
@@ -388,10 +454,11 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
     return JABBA_OK;
 }
 
-int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag) {
+int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag,
+                     bool keep_keys) {
     const bool main_sort = !tag || !tag[0];
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
-    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, b.ctl, b.gbase);
+    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, keep_keys ? 1 : 0, b.ctl, b.gbase);
     JB_LAUNCH_CHECK();
     for (int pass = 0; pass < 8; ++pass) {
         JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups", main_sort ? k_onesweep<0> : k_onesweep<1>,

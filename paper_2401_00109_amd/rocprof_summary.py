@@ -47,7 +47,7 @@ def timing_name(kernel: str) -> str:
         return "k_compress_znorm" if ("true" in targs or "(bool)1" in targs) else "k_compress<W>"
     if base == "k_onesweep":
         return base + ("_groups" if targs == "<1>" else "")
-    if base == "k_key":
+    if base in ("k_key", "k_gather"):
         return base + ("_pca" if targs == "<1>" else "")
     return base + targs
 
