@@ -496,7 +496,8 @@ int jabba_plan_create(const jabba_plan_desc *desc, jabba_plan **plan);
 /* Replays the captured graph on `stream` (asynchronous). */
 int jabba_plan_run(jabba_plan *plan, void *stream);
 
-/* Frees the graph; buffers stay with the caller. */
+/* Frees the graph; buffers stay with the caller.  The plan is freed in every
+ * case; JABBA_EHIP if the runtime reported an error while destroying it. */
 int jabba_plan_destroy(jabba_plan *plan);
 
 #ifdef __cplusplus

@@ -22,7 +22,7 @@ extern "C" int jabba_plan_create(const jabba_plan_desc *d, jabba_plan **out) {
     int rc = JABBA_OK;
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        hipStreamDestroy(st);
+        (void)hipStreamDestroy(st);  // the capture error is the one reported
         return JABBA_EHIP;
     }
     rc = jabba_compress(d->values, d->series_off, d->n_series, d->total_points, d->D, d->tol, d->max_len, &d->tuning,
@@ -37,12 +37,13 @@ extern "C" int jabba_plan_create(const jabba_plan_desc *d, jabba_plan **out) {
         p = new jabba_plan{graph, nullptr};
         if (hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = JABBA_EHIP;
     }
-    if (rc != JABBA_OK) {
-        if (graph) hipGraphDestroy(graph);
+    if (hipStreamDestroy(st) != hipSuccess && rc == JABBA_OK) rc = JABBA_EHIP;
+    if (rc != JABBA_OK) {  // cleanup after a failure; the first error is the one reported
+        if (p && p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (graph) (void)hipGraphDestroy(graph);
         delete p;
         p = nullptr;
     }
-    hipStreamDestroy(st);
     *out = p;
     return rc;
 }
@@ -55,8 +56,8 @@ extern "C" int jabba_plan_run(jabba_plan *plan, void *stream) {
 
 extern "C" int jabba_plan_destroy(jabba_plan *plan) {
     if (!plan) return JABBA_OK;
-    if (plan->exec) hipGraphExecDestroy(plan->exec);
-    if (plan->graph) hipGraphDestroy(plan->graph);
+    const hipError_t e1 = plan->exec ? hipGraphExecDestroy(plan->exec) : hipSuccess;
+    const hipError_t e2 = plan->graph ? hipGraphDestroy(plan->graph) : hipSuccess;
     delete plan;
-    return JABBA_OK;
+    return e1 == hipSuccess && e2 == hipSuccess ? JABBA_OK : JABBA_EHIP;
 }
