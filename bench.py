@@ -93,7 +93,7 @@ def main() -> int:
                     help="also run a plain 1 GiB copy kernel (for rocprofv3 counter scaling)")
     ap.add_argument("--tuning", default=None, help="JSON dict of jabba_tuning fields")
     ap.add_argument("--pipeline", type=int, default=0,
-                    help="buffer sets in flight (one stream each); 0 = 2 up to 2e8 points, else 1")
+                    help="buffer sets in flight (one stream each); 0 = 3 up to 2e8 points, else 1")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -155,7 +155,9 @@ def main() -> int:
     # buffer sets, one stream each, so batch i+1's compression (a few
     # wavefronts per compute unit) overlaps batch i's digitization and
     # reconstruction; every batch still does all of its work.
-    n_sets = args.pipeline if args.pipeline > 0 else (2 if w.n_points <= 200_000_000 else 1)
+    # three streams plus the default one fill the process's four hardware
+    # queues; a fourth set in flight measured slower than three
+    n_sets = args.pipeline if args.pipeline > 0 else (3 if w.n_points <= 200_000_000 else 1)
 
     def make_set(sz_, full_, enc_, rec_):
         return {"sz": sz_, "full": full_, "enc": enc_, "rec": rec_, "st": torch.cuda.Stream(device=dev),
