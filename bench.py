@@ -97,7 +97,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library and its benchmark run on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         log("only --gpus 1 is supported: the library and its benchmark are single-GPU")
         return 2

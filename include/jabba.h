@@ -397,7 +397,9 @@ int jabba_reconstruct_size(const int32_t *symbols, const int64_t *piece_off, con
  * out[out_off[n_series]]: out.  lhat[max pieces]: optional out (may be NULL).
  * values/series_off: optional originals; when values is non-NULL, sse[s] and
  * cnt[s] receive the squared error over the first min(n_s, n^_s) points
- * (Sec. 3.3, MSE = sum(sse)/sum(cnt)).
+ * (Sec. 3.3, MSE = sum(sse)/sum(cnt)).  dict->capacity >= 1, else
+ * JABBA_EINVAL; a symbol outside [0, capacity) reads as length 1, increment 0
+ * (jabba_reconstruct_size flags it in the device status).
  */
 int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off, int64_t n_series,
                       const double *t0, const jabba_dict *dict, const int64_t *out_off, double *out, int64_t *lhat,

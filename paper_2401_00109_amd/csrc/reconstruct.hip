@@ -137,6 +137,29 @@ struct Src {
         }
     }
     __device__ void get(int64_t j, u128 &lt, double &it, bool &ok) const { convert(load(j, tag(j)), lt, it, ok); }
+    // Branch-free forms of tag() and load() for a prefetch pipeline: every
+    // load is issued (indices are clamped by the caller, an invalid symbol
+    // reads center 0 and is flagged), so the loaded registers are the
+    // loop-carried ones and nothing waits for them before their use.
+    // Dictionary form needs k >= 1.
+    template <bool Dict>
+    __device__ int32_t tag_at(int64_t j) const {
+        return Dict ? sym[j] : 0;
+    }
+    template <bool Dict>
+    __device__ Raw fetch(int64_t j, int32_t c) const {
+        Raw r{0.0, 0.0, 0, false};
+        if (Dict) {
+            r.bad = c < 0 || c >= k;
+            const int64_t cc = r.bad ? 0 : c;
+            r.l = center_len[cc];
+            r.it = center_inc[cc];
+        } else {
+            r.li = len[j];
+            r.it = inc[j];
+        }
+        return r;
+    }
 };
 
 __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__restrict__ piece_off,
@@ -168,7 +191,8 @@ __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__r
 // One workgroup per series.  Wavefront 0 produces chunks of 64 pieces (the
 // fixed-point scan of the lengths and the sequential values) into LDS while
 // the next chunk's loads are in flight; wavefront 1 fills the points of the
-// previous chunk, one point per thread (coalesced stores).  The two LDS
+// previous chunk, one point per thread (coalesced stores), with the original
+// values for the squared error loaded four points at a time.  The two LDS
 // buffers alternate, one barrier per chunk.
 struct ReconChunk {
     int64_t beg[kWave];  // S_{j-1}: offset of the piece's first point (its predecessor's end)
@@ -185,6 +209,7 @@ constexpr int kFillThreads = kReconThreads - kWave;
 // original series over the common prefix m = min(n, n^): each filler thread
 // sums its own points in order, and the 64 partials are added by one fixed
 // tree per series (deterministic).
+template <bool Dict>
 __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t *__restrict__ piece_off,
                                                          const int64_t *__restrict__ out_off, int64_t n_series,
                                                          const double *__restrict__ t0, double *__restrict__ out,
@@ -194,7 +219,8 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
                                                          double *__restrict__ sse, int64_t *__restrict__ sse_cnt) {
     __shared__ ReconChunk buf[2];
     const int lane = lane_id();
-    const bool producer = threadIdx.x < kWave;
+    // uniform per wavefront, and known to be: the roles branch on a scalar
+    const bool producer = __builtin_amdgcn_readfirstlane(threadIdx.x) < kWave;
     for (int64_t s = blockIdx.x; s < n_series; s += gridDim.x) {
         const int64_t a = piece_off[s], b = piece_off[s + 1];
         const int64_t o = out_off[s];
@@ -214,6 +240,10 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
         u128 carryC = 0;
         int64_t carryS = 0;
         double V = 0.0;
+        // loads of the next chunk (raw_n) and of the symbols two chunks
+        // ahead (tag_n); indices past the series' last piece are clamped to
+        // it and their results never used
+        auto clampj = [&](int64_t j) -> int64_t { return j < b ? j : b - 1; };
         Src::Raw raw_n{0.0, 0.0, 0, false};
         int32_t tag_n = 0;
         if (producer) {
@@ -221,24 +251,27 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
             if (lane == 0 && out_off[s + 1] > o) out[o] = V;
             if (nch > 0) {
                 const int64_t j = a + lane;
-                if (j < b) raw_n = src.load(j, src.tag(j));
-                if (j + kWave < b) tag_n = src.tag(j + kWave);
+                raw_n = src.fetch<Dict>(clampj(j), src.tag_at<Dict>(clampj(j)));
+                tag_n = src.tag_at<Dict>(clampj(j + kWave));
             }
         }
-        for (int64_t t = 0; t <= nch; ++t) {
+        // chunk t: cur holds its loads, tcur the symbols of chunk t + 1; the
+        // step loads chunk t + 1 into nxt and the symbols of chunk t + 2 into
+        // tnxt.  The loop below alternates the two register sets, so a load
+        // lands in a register nothing reads until the next chunk.
+        auto step = [&](int64_t t, const Src::Raw &cur, Src::Raw &nxt, const int32_t &tcur, int32_t &tnxt) {
             if (producer && t < nch) {
                 const int64_t j0 = a + t * kWave;
                 const int64_t j = j0 + lane;
                 u128 lt = 0;
                 double it = 0.0;
+                // the next chunk's loads, consumed one chunk later
+                nxt = src.fetch<Dict>(clampj(j + kWave), tcur);
+                tnxt = src.tag_at<Dict>(clampj(j + 2 * kWave));
                 if (j < b) {
                     bool ok = true;
-                    src.convert(raw_n, lt, it, ok);
+                    src.convert(cur, lt, it, ok);
                 }
-                // the next chunk's loads, consumed one chunk later
-                raw_n = Src::Raw{0.0, 0.0, 0, false};
-                if (j + kWave < b) raw_n = src.load(j + kWave, tag_n);
-                tag_n = (j + 2 * kWave < b) ? src.tag(j + 2 * kWave) : 0;
                 // inclusive scan of the fixed-point center lengths
                 u128 C = wave_incl_scan_u128(lt) + carryC;
                 const int64_t S = fixed_round(C);
@@ -276,28 +309,47 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
                 const ReconChunk &B = buf[tc & 1];
                 const int64_t lo = B.beg[0], hi = B.end[cnt - 1];
                 const int f = threadIdx.x - kWave;
-                for (int64_t r = lo + 1 + f; r <= hi; r += kFillThreads) {
-                    // first piece whose end is at or after point r
-                    int L = 0, H = cnt - 1;
-                    while (L < H) {
-                        const int M = (L + H) >> 1;
-                        if (B.end[M] >= r)
-                            H = M;
-                        else
-                            L = M + 1;
+                constexpr int kAhead = 4;  // points per thread whose originals are loaded together
+                for (int64_t r0 = lo + 1 + f; r0 <= hi; r0 += kAhead * kFillThreads) {
+                    double orig[kAhead];
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) {
+                        const int64_t r = r0 + (int64_t)u * kFillThreads;
+                        orig[u] = (r <= hi && r < m_err) ? values[vo + r] : 0.0;
                     }
-                    const double vprev = L > 0 ? B.vme[L - 1] : B.vin;
-                    const double vr = (r == B.end[L]) ? B.vme[L] : vprev + B.slope[L] * (double)(r - B.beg[L]);
-                    out[o + r] = vr;
-                    if (r < m_err) {
-                        const double d = values[vo + r] - vr;
-                        err = err + d * d;
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) {
+                        const int64_t r = r0 + (int64_t)u * kFillThreads;
+                        if (r > hi) break;
+                        // first piece whose end is at or after point r
+                        int L = 0, H = cnt - 1;
+                        while (L < H) {
+                            const int M = (L + H) >> 1;
+                            if (B.end[M] >= r)
+                                H = M;
+                            else
+                                L = M + 1;
+                        }
+                        const double vprev = L > 0 ? B.vme[L - 1] : B.vin;
+                        const double vr =
+                            (r == B.end[L]) ? B.vme[L] : vprev + B.slope[L] * (double)(r - B.beg[L]);
+                        out[o + r] = vr;
+                        if (r < m_err) {  // each thread adds its points in increasing r
+                            const double d = orig[u] - vr;
+                            err = err + d * d;
+                        }
                     }
                 }
                 if (lhat)
                     for (int l = f; l < cnt; l += kFillThreads) lhat[j0 + l] = B.end[l] - B.beg[l];
             }
             __syncthreads();
+        };
+        Src::Raw raw_b{0.0, 0.0, 0, false};
+        int32_t tag_b = 0;
+        for (int64_t t = 0; t <= nch; t += 2) {
+            step(t, raw_n, raw_b, tag_n, tag_b);
+            if (t + 1 <= nch) step(t + 1, raw_b, raw_n, tag_b, tag_n);
         }
         if (values && !producer) {
             const double tot = wave_tree_sum(err);
@@ -387,13 +439,14 @@ extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_of
                                  double *out, int64_t *lhat, const double *values, double *sse, int64_t *cnt,
                                  void *stream) {
     if (!dict || !dict->center_len || !dict->center_inc || n_series < 0 || !piece_off || !out_off) return JABBA_EINVAL;
+    if (dict->capacity < 1) return JABBA_EINVAL;
     if (n_series == 0) return JABBA_OK;
     if (!t0 || !out || !series_off) return JABBA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
     if (values && (!sse || !cnt)) return JABBA_EINVAL;
-    JB_LAUNCH(k_recon, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off, out_off, n_series,
-              t0, out, lhat, series_off, values, sse, cnt);
+    JB_LAUNCH_NAMED("k_recon", k_recon<true>, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off,
+                    out_off, n_series, t0, out, lhat, series_off, values, sse, cnt);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -407,9 +460,9 @@ extern "C" int jabba_reconstruct_pieces(const int32_t *len, const double *inc, c
     int rc = sizes(src, piece_off, series_off, n_series, out_off, workspace, workspace_bytes, st);
     if (rc || n_series == 0) return rc;
     if (!t0 || !out) return JABBA_EINVAL;
-    JB_LAUNCH(k_recon, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off, out_off, n_series,
-              t0, out, (int64_t *)nullptr, series_off, (const double *)nullptr, (double *)nullptr,
-              (int64_t *)nullptr);
+    JB_LAUNCH_NAMED("k_recon_pieces", k_recon<false>, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src,
+                    piece_off, out_off, n_series, t0, out, (int64_t *)nullptr, series_off, (const double *)nullptr,
+                    (double *)nullptr, (int64_t *)nullptr);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }

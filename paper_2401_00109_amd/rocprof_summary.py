@@ -49,6 +49,8 @@ def timing_name(kernel: str) -> str:
         return base + ("_groups" if targs == "<1>" else "")
     if base in ("k_key", "k_gather"):
         return base + ("_pca" if targs == "<1>" else "")
+    if base == "k_recon":
+        return "k_recon" if ("true" in targs or "(bool)1" in targs) else "k_recon_pieces"
     return base + targs
 
 
