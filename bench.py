@@ -136,76 +136,28 @@ def main() -> int:
     torch.cuda.synchronize()
     N = probe.count()
     del probe
-    sz = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B, max_pieces=max(N, 1),
-                      capacity=max(N, 1), tuning=tuning)
-    # compress writes up to sum(n_s - 1) pieces in the worst case: give it that capacity
-    full = J.Pieces(torch.empty(max(w.n_points, 1), dtype=torch.int32, device=dev),
-                    torch.empty(max(w.n_points, 1), dtype=torch.float64, device=dev),
-                    sz.pieces.piece_off, sz.pieces.n_pieces, max(w.n_points, 1))
-    sz.pieces = full
-    enc = torch.empty(max(w.n_points, 1), dtype=torch.int32, device=dev)
-    rec = J.Reconstructor(full.piece_off, so, t0, v)
+    # One step = compress, encode against the resident dictionary, digitize,
+    # reconstruct, for one batch.  Consecutive steps go to consecutive buffer
+    # sets, one stream each, so one batch's compression (a few wavefronts per
+    # compute unit) overlaps the others' digitization and reconstruction;
+    # every step still does all of its work.  Three streams plus the default
+    # one fill the process's four hardware queues; a fourth set in flight
+    # measured slower than three.
+    from paper_2401_00109_amd.pipeline import Pipeline
+    n_sets = args.pipeline if args.pipeline > 0 else (3 if w.n_points <= 200_000_000 else 1)
+    pipe = Pipeline(v, so, t0, w.D, w.tol, w.alpha, w.scl, w.B, N, resident, n_sets=n_sets, tuning=tuning,
+                    max_len=w.max_len)
+    sets = pipe.sets
+    S0 = sets[0]
+    sz, full, enc, rec = S0.sz, S0.pieces, S0.enc, S0.rec
 
     def step_sym():
         sz.compress(v, so)
         sz.digitize()
 
-    # One step = compress, encode against the resident dictionary, digitize,
-    # reconstruct, for one batch.  Consecutive batches alternate between
-    # buffer sets, one stream each, so batch i+1's compression (a few
-    # wavefronts per compute unit) overlaps batch i's digitization and
-    # reconstruction; every batch still does all of its work.
-    # three streams plus the default one fill the process's four hardware
-    # queues; a fourth set in flight measured slower than three
-    n_sets = args.pipeline if args.pipeline > 0 else (3 if w.n_points <= 200_000_000 else 1)
-
-    def make_set(sz_, full_, enc_, rec_):
-        return {"sz": sz_, "full": full_, "enc": enc_, "rec": rec_, "st": torch.cuda.Stream(device=dev),
-                "ews": J.api._ws(J.api.encode_workspace_bytes(resident.capacity), dev)}
-
-    sets = [make_set(sz, full, enc, rec)]
-
-    def step_set(S):
-        st = S["st"]
-        S["sz"].compress(v, so, stream=st)
-        J.encode(S["full"].len, S["full"].inc, S["full"].n_pieces, N, resident, symbols=S["enc"],
-                 workspace=S["ews"], stream=st)
-        S["sz"].digitize(stream=st)
-        S["rec"].run(S["sz"].symbols, S["sz"].dictionary, stream=st)
-
-    def fork():
-        ev = torch.cuda.Event()
-        ev.record()
-        for S in sets:
-            S["st"].wait_event(ev)
-
-    def join():
-        for S in sets:
-            ev = torch.cuda.Event()
-            ev.record(S["st"])
-            torch.cuda.current_stream().wait_event(ev)
-
     def run_steps(n, pipelined=True):
-        fork()
-        for i in range(n):
-            step_set(sets[i % len(sets)] if pipelined else sets[0])
-        join()
+        pipe.run(n, pipelined=pipelined)
 
-
-    step_sym()
-    rec.size(sz.symbols, sz.dictionary)
-    for _ in range(1, n_sets):
-        sz_b = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B, max_pieces=max(N, 1),
-                            capacity=max(N, 1), tuning=tuning)
-        full_b = J.Pieces(torch.empty(max(w.n_points, 1), dtype=torch.int32, device=dev),
-                          torch.empty(max(w.n_points, 1), dtype=torch.float64, device=dev),
-                          sz_b.pieces.piece_off, sz_b.pieces.n_pieces, max(w.n_points, 1))
-        sz_b.pieces = full_b
-        rec_b = J.Reconstructor(full_b.piece_off, so, t0, v)
-        sz_b.compress(v, so)
-        sz_b.digitize()
-        rec_b.size(sz_b.symbols, sz_b.dictionary)
-        sets.append(make_set(sz_b, full_b, torch.empty(max(w.n_points, 1), dtype=torch.int32, device=dev), rec_b))
     run_steps(max(args.warmup, 1) * len(sets))
     torch.cuda.synchronize()
     st = sz.status()
@@ -229,9 +181,9 @@ def main() -> int:
     ms_step = ev0.elapsed_time(ev1) / args.steps
     value = w.n_points / (ms_step / 1e3)
     for S in sets[1:]:
-        assert torch.equal(S["sz"].symbols[:N], sz.symbols[:N]) and torch.equal(S["enc"][:N], enc[:N]), \
+        assert torch.equal(S.sz.symbols[:N], sz.symbols[:N]) and torch.equal(S.enc[:N], enc[:N]), \
             "buffer sets disagree"
-        assert S["sz"].status() == (0, 0)
+        assert S.sz.status() == (0, 0)
     ev0.record()
     run_steps(args.steps, pipelined=False)
     ev1.record()

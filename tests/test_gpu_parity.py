@@ -360,30 +360,77 @@ def test_plan_graph_replays_match_eager():
 
 
 # ------------------------------------------------------------------ full size
-def test_full_size_scale_workload():
-    """4,096 x 10,000 points, the launch configuration the benchmark times."""
+@pytest.fixture(scope="module")
+def full_scale():
+    """The 4,096 x 10,000-point workload and the oracle's pieces and digitization."""
+    w = make_workload(2, seed=0)
+    say(f"full-size workload 2: {w.n_series} series, {w.n_points} points; oracle compress + digitize")
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    od = O.digitize(ol, oi, w.alpha, w.scl, w.B)
+    return w, ol, oi, opo, od
+
+
+def test_full_size_scale_workload(full_scale):
+    """4,096 x 10,000 points through one Symbolizer on the default stream."""
     import paper_2401_00109_amd as J
     T = torch()
-    w = make_workload(2, seed=0)
-    say(f"full-size workload 2: {w.n_series} series, {w.n_points} points")
+    w, ol, oi, opo, od = full_scale
     v, so = to_dev(w.values), to_dev(w.series_off)
     sz = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B)
     sz.run(v, so)
     T.cuda.synchronize()
     assert sz.status() == (0, 0)
     ln, inc, po = sz.pieces.host()
-    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
     np.testing.assert_array_equal(po, opo)
     np.testing.assert_array_equal(ln, ol)
     np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
-    say(f"  compress parity ok: N={ol.size}; running the oracle's digitize")
-    od = O.digitize(ol, oi, w.alpha, w.scl, w.B)
+    say(f"  compress parity ok: N={ol.size}")
     d = sz.dictionary.host()
     assert d["k"] == od.k
     np.testing.assert_array_equal(sz.symbols[: ol.size].cpu().numpy(), od.symbols)
     np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
     worst = assert_centers_close(d, od, oi, od.symbols)
     say(f"  digitize parity ok: k={od.k} G={od.n_starts} center_inc worst rel {worst:.3e}")
+
+
+def test_full_size_pipelined_step(full_scale):
+    """The benchmark's timed configuration: three buffer sets on three
+    streams, each step compress, encode against the resident dictionary,
+    digitize and reconstruct (with the squared error).  After two steps per
+    set, every set's symbols equal the oracle's; its encodings equal the
+    oracle's nearest centers on a sample of pieces (every 16th, and both
+    ends); its reconstruction equals, bit for bit, the oracle's
+    reconstruction from the set's own dictionary, whose lengths are the
+    oracle's bit for bit and whose increments are within the centers'
+    tolerance."""
+    from paper_2401_00109_amd.pipeline import Pipeline
+    from paper_2401_00109_amd.serve import build_resident_dictionary
+    T = torch()
+    w, ol, oi, opo, od = full_scale
+    N = ol.size
+    v, so = to_dev(w.values), to_dev(w.series_off)
+    t0h = np.where(np.diff(w.series_off) > 0, w.values[np.minimum(w.series_off[:-1], max(w.n_points - 1, 0))], 0.0)
+    resident = build_resident_dictionary(DEV)
+    say(f"pipelined full step, 3 sets, resident k={resident.size()}")
+    pipe = Pipeline(v, so, to_dev(t0h), w.D, w.tol, w.alpha, w.scl, w.B, N, resident, n_sets=3)
+    pipe.run(6)
+    T.cuda.synchronize()
+    rd = resident.host()
+    idx = np.unique(np.concatenate([np.arange(0, N, 16), np.arange(min(1000, N)), np.arange(max(N - 1000, 0), N)]))
+    enc_exp = O.encode(ol[idx], oi[idx], rd["sigma_len"], rd["sigma_inc"], rd["scl"], rd["cx"], rd["cy"])
+    for i, S in enumerate(pipe.sets):
+        assert S.steps == 2 and S.sz.status() == (0, 0)
+        np.testing.assert_array_equal(S.sz.symbols[:N].cpu().numpy(), od.symbols)
+        np.testing.assert_array_equal(S.enc[:N].cpu().numpy()[idx], enc_exp)
+        d = S.sz.dictionary.host()
+        np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
+        out, oo, _, sse, cnt = O.reconstruct(od.symbols, opo, w.series_off, t0h, d["center_len"], d["center_inc"],
+                                             orig=w.values)
+        np.testing.assert_array_equal(S.rec.out_off.cpu().numpy(), oo)
+        np.testing.assert_array_equal(S.rec.out[: out.size].cpu().numpy().view(np.uint64), out.view(np.uint64))
+        np.testing.assert_array_equal(S.rec.cnt[: w.n_series].cpu().numpy(), cnt)
+        np.testing.assert_allclose(S.rec.sse[: w.n_series].cpu().numpy(), sse, rtol=1e-12, atol=1e-300)
+        say(f"  set {i}: symbols, {idx.size} sampled encodings and {out.size} reconstructed points ok")
 
 
 def _gpu_encode(ln, inc, sl, si, scl, cx, cy):
