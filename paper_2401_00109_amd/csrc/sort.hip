@@ -215,18 +215,19 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wave
 // A pass over one tile of kTileN pairs with kSweepThreads threads: threads
 // below 256 own one digit each (histogram, look-back, bucket bases).  The
 // per-wave digit counts and the tile histogram share LDS with the staged
-// keys (they are dead before the tile is staged).
+// keys (they are dead before the tile is staged), and the values are loaded
+// only for the staging, after the look-back: 51 KB of LDS and at most 80
+// registers let three workgroups share a compute unit, so one tile's
+// look-back and loads overlap the others' work.
 constexpr int kSweepThreads = 512;
 constexpr int kSweepRounds = kTileN / kSweepThreads;
+constexpr int kSweepWavesPerSimd = 6;
 
 template <int Tag>
-__global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
-                                                            uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
-                                                            const int64_t *n_dev, int64_t n_max, int shift,
-                                                            int32_t *ctl, int pass, const uint32_t *__restrict__ gbase,
-                                                            const unsigned long long *__restrict__ kmin,
-                                                            uint64_t *__restrict__ status,
-                                                            int32_t *__restrict__ tile_ctr) {
+__global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
+    uint64_t *__restrict__ k0, uint64_t *__restrict__ k1, uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
+    const int64_t *n_dev, int64_t n_max, int shift, int32_t *ctl, int pass, const uint32_t *__restrict__ gbase,
+    const unsigned long long *__restrict__ kmin, uint64_t *__restrict__ status, int32_t *__restrict__ tile_ctr) {
     if (ctl[kCtlSkip + pass]) return;
     constexpr int kWaves = kSweepThreads / kWave;
     constexpr int kPerWave = kTileN / kWaves;  // contiguous slice of the tile per wavefront
@@ -279,12 +280,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
     // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
     // (wave, round, lane) order is index order; all loads in flight at once
     uint64_t kr[kSweepRounds];
-    uint32_t vr[kSweepRounds];
 #pragma unroll
     for (int r = 0; r < kSweepRounds; ++r) {
         const int li = w * kPerWave + r * kWave + lane;
         kr[r] = li < m ? (in32 ? (uint64_t)ks32[base + li] : ks[base + li]) : 0ull;
-        vr[r] = li < m ? vs[base + li] : 0u;
     }
     // per element: its digit, later (wave-local rank << 8 | digit), later its
     // slot in the ranked tile (one register per element across the look-back)
@@ -328,7 +327,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
     // first until a prefix is found, waiting only on words not yet published.
     uint64_t excl = 0;
     if (digit_owner && tile > 0) {
-        constexpr int kWindow = 4;
+        constexpr int kWindow = 2;
         const uint64_t ready_tag = (uint64_t)(pass + 1);
         int64_t t = tile - 1;
         int spins = 0;
@@ -383,6 +382,12 @@ __global__ __launch_bounds__(kSweepThreads) void k_onesweep(uint64_t *__restrict
         dp[r] = (dp[r] >> 8) + s_lo[dg] + s_wrun[w][dg];  // slot in the ranked tile
     }
     __syncthreads();  // the counts are read; their storage becomes the staged keys
+    uint32_t vr[kSweepRounds];
+#pragma unroll
+    for (int r = 0; r < kSweepRounds; ++r) {
+        const int li = w * kPerWave + r * kWave + lane;
+        vr[r] = li < m ? vs[base + li] : 0u;
+    }
 #pragma unroll
     for (int r = 0; r < kSweepRounds; ++r) {
         if (w * kPerWave + r * kWave + lane < m) {
