@@ -199,9 +199,11 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
 // Sorts n (device count) pairs held in keys[0]/vals[0]; the result is in
 // keys[ctl[0]], vals[ctl[0]] (read on device by consumers).  With keep_keys
 // false only vals[ctl[0]] holds the result (the sorted order); the key
-// buffers then hold intermediate, narrowed keys.
+// buffers then hold intermediate, narrowed keys.  sparse: the live count is
+// expected far below n_max (the passes then run persistent workgroups
+// instead of one per possible tile).
 // `tag` suffixes the timing names of the pass kernels ("" for the main sort).
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st,
-                     const char *tag = "", bool keep_keys = true);
+                     const char *tag = "", bool keep_keys = true, bool sparse = false);
 
 }  // namespace jabba

@@ -1408,7 +1408,7 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     JB_LAUNCH_CHECK();
     rc = radix_global_hist(w.sb, w.g_count, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups");
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups", /*keep_keys=*/true, /*sparse=*/true);
     if (rc) return rc;
     JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
               w.sb.vals[1], w.sb.ctl, w.gk,
@@ -1506,7 +1506,7 @@ extern "C" int jabba_aggregate_points(const double *x, const double *y, const in
     JB_LAUNCH_CHECK();
     rc = radix_global_hist(w.sb, w.g_count, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups");
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups", /*keep_keys=*/true, /*sparse=*/true);
     if (rc) return rc;
     JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
               w.sb.vals[1], w.sb.ctl, w.gk, w.gx, w.gy, alpha, w.cut, w.ord, w.ck, w.cx, w.cy);

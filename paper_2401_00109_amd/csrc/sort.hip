@@ -223,7 +223,7 @@ constexpr int kSweepThreads = 512;
 constexpr int kSweepRounds = kTileN / kSweepThreads;
 constexpr int kSweepWavesPerSimd = 6;
 
-template <int Tag>
+template <int Tag, bool Persistent>
 __global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
     uint64_t *__restrict__ k0, uint64_t *__restrict__ k1, uint32_t *__restrict__ v0, uint32_t *__restrict__ v1,
     const int64_t *n_dev, int64_t n_max, int shift, int32_t *ctl, int pass, const uint32_t *__restrict__ gbase,
@@ -251,165 +251,172 @@ __global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
     const int w = tid / kWave;
     const int lane = tid & (kWave - 1);
     const bool digit_owner = tid < 256;
-    if (tid == 0) s_tile = atomicAdd(&tile_ctr[pass], 1);
-    if (digit_owner) {
-        s_hist[tid] = 0;
-        for (int q = 0; q < kWaves; ++q) s_wrun[q][tid] = 0;
-    }
-    __syncthreads();
-    const int64_t tile = s_tile;
-    const int64_t n = live(n_dev, n_max);
-    const int64_t base = tile * kTileN;
-    if (base >= n) return;
-    const bool src1 = ctl[kCtlSrc + pass] != 0;
-    const uint64_t *ks = src1 ? k1 : k0;
-    const uint32_t *vs = src1 ? v1 : v0;
-    uint64_t *kd = src1 ? k0 : k1;
-    uint32_t *vd = src1 ? v0 : v1;
-    const int m = (int)(n - base < kTileN ? n - base : kTileN);
-    const uint64_t kbase = *kmin;
-    const int mode = ctl[kCtlMode + pass];
-    const bool in32 = (mode & kModeIn32) != 0;
-    const int nshift = ctl[kCtlBase];  // 32-bit keys hold key - kmin from this bit up
-    // 64-bit keys are held as read; 32-bit keys are zero-extended
-    auto digit = [&](uint64_t key) -> uint32_t {
-        return in32 ? (uint32_t)(key >> (shift - nshift)) & 255u : (uint32_t)((key - kbase) >> shift) & 255u;
-    };
-    const uint32_t *ks32 = reinterpret_cast<const uint32_t *>(ks);
-
-    // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
-    // (wave, round, lane) order is index order; all loads in flight at once
-    uint64_t kr[kSweepRounds];
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        const int li = w * kPerWave + r * kWave + lane;
-        kr[r] = li < m ? (in32 ? (uint64_t)ks32[base + li] : ks[base + li]) : 0ull;
-    }
-    // per element: its digit, later (wave-local rank << 8 | digit), later its
-    // slot in the ranked tile (one register per element across the look-back)
-    uint32_t dp[kSweepRounds];
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        dp[r] = digit(kr[r]);
-        if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[dp[r]], 1u);
-    }
-    __syncthreads();
-    const uint32_t cnt = digit_owner ? s_hist[tid] : 0u;
-
-    // publish this tile's counts early, so later tiles' look-backs find them
-    const uint64_t tag = (uint64_t)(pass + 1) << 56;
-    if (digit_owner)
-        __hip_atomic_store(&status[tile * 256 + tid], tag | (tile == 0 ? kFlagPre : kFlagAgg) | cnt,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
-    // wave-local ranking in index order: peers with the same digit by eight
-    // ballots, a running count per digit in this wave's LDS row
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        const bool ok = w * kPerWave + r * kWave + lane < m;
-        const uint32_t dg = dp[r];
-        uint64_t peers = __ballot(ok);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (dg >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
+    // one tile per workgroup, or (Persistent) tiles in ticket order until
+    // none is left; a workgroup holds a ticket only while it works on that
+    // tile, so every look-back waits on tiles that are running or done
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(&tile_ctr[pass], 1);
+        if (digit_owner) {
+            s_hist[tid] = 0;
+            for (int q = 0; q < kWaves; ++q) s_wrun[q][tid] = 0;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        const uint32_t run = s_wrun[w][dg];
-        dp[r] |= (run + rank) << 8;
-        if (ok && rank == 0) s_wrun[w][dg] = run + (uint32_t)__popcll(peers);
-    }
+        __syncthreads();
+        const int64_t tile = s_tile;
+        const int64_t n = live(n_dev, n_max);
+        const int64_t base = tile * kTileN;
+        if (base >= n) break;
+        const bool src1 = ctl[kCtlSrc + pass] != 0;
+        const uint64_t *ks = src1 ? k1 : k0;
+        const uint32_t *vs = src1 ? v1 : v0;
+        uint64_t *kd = src1 ? k0 : k1;
+        uint32_t *vd = src1 ? v0 : v1;
+        const int m = (int)(n - base < kTileN ? n - base : kTileN);
+        const uint64_t kbase = *kmin;
+        const int mode = ctl[kCtlMode + pass];
+        const bool in32 = (mode & kModeIn32) != 0;
+        const int nshift = ctl[kCtlBase];  // 32-bit keys hold key - kmin from this bit up
+        // 64-bit keys are held as read; 32-bit keys are zero-extended
+        auto digit = [&](uint64_t key) -> uint32_t {
+            return in32 ? (uint32_t)(key >> (shift - nshift)) & 255u : (uint32_t)((key - kbase) >> shift) & 255u;
+        };
+        const uint32_t *ks32 = reinterpret_cast<const uint32_t *>(ks);
 
-    // look-back: this tile's offset inside bucket `tid`.  The status words of
-    // kWindow earlier tiles are read together; they are consumed newest
-    // first until a prefix is found, waiting only on words not yet published.
-    uint64_t excl = 0;
-    if (digit_owner && tile > 0) {
-        constexpr int kWindow = 2;
-        const uint64_t ready_tag = (uint64_t)(pass + 1);
-        int64_t t = tile - 1;
-        int spins = 0;
-        bool done = false;
-        while (!done) {
-            uint64_t v[kWindow];
-#pragma unroll
-            for (int i = 0; i < kWindow; ++i)
-                v[i] = t - i >= 0 ? __hip_atomic_load(&status[(t - i) * 256 + tid], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)
-                                  : 0ull;  // never consumed: tile 0 always holds a prefix
-#pragma unroll
-            for (int i = 0; i < kWindow; ++i) {
-                if (done) break;
-                uint64_t x = v[i];
-                while ((x >> 56) != ready_tag || (x & (kFlagAgg | kFlagPre)) == 0) {
-                    if (++spins > kSpinLimit) {  // cannot happen while every earlier tile runs; bail out loudly
-                        __hip_atomic_store(&ctl[kCtlError], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        x = ready_tag << 56 | kFlagPre;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    x = __hip_atomic_load(&status[(t - i) * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                excl += x & kCountMask;
-                if (x & kFlagPre) done = true;
+        // element (w, r, lane) is tile element w * kPerWave + r * 64 + lane, so
+        // (wave, round, lane) order is index order; all loads in flight at once
+        uint64_t kr[kSweepRounds];
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            const int li = w * kPerWave + r * kWave + lane;
+            kr[r] = li < m ? (in32 ? (uint64_t)ks32[base + li] : ks[base + li]) : 0ull;
+        }
+        // per element: its digit, later (wave-local rank << 8 | digit), later its
+        // slot in the ranked tile (one register per element across the look-back)
+        uint32_t dp[kSweepRounds];
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            dp[r] = digit(kr[r]);
+            if (w * kPerWave + r * kWave + lane < m) atomicAdd(&s_hist[dp[r]], 1u);
+        }
+        __syncthreads();
+        const uint32_t cnt = digit_owner ? s_hist[tid] : 0u;
+
+        // publish this tile's counts early, so later tiles' look-backs find them
+        const uint64_t tag = (uint64_t)(pass + 1) << 56;
+        if (digit_owner)
+            __hip_atomic_store(&status[tile * 256 + tid], tag | (tile == 0 ? kFlagPre : kFlagAgg) | cnt,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+        // wave-local ranking in index order: peers with the same digit by eight
+        // ballots, a running count per digit in this wave's LDS row
+        const uint64_t lt = lanemask_lt();
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            const bool ok = w * kPerWave + r * kWave + lane < m;
+            const uint32_t dg = dp[r];
+            uint64_t peers = __ballot(ok);
+    #pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (dg >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
             }
-            t -= kWindow;
+            const uint32_t rank = (uint32_t)__popcll(peers & lt);
+            const uint32_t run = s_wrun[w][dg];
+            dp[r] |= (run + rank) << 8;
+            if (ok && rank == 0) s_wrun[w][dg] = run + (uint32_t)__popcll(peers);
         }
-        __hip_atomic_store(&status[tile * 256 + tid], tag | kFlagPre | ((excl + cnt) & kCountMask), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();  // every wave's counts are final
-    if (digit_owner) {
-        uint32_t acc = 0;
-#pragma unroll
-        for (int q = 0; q < kWaves; ++q) {
-            const uint32_t c = s_wrun[q][tid];
-            s_wrun[q][tid] = acc;
-            acc += c;
+
+        // look-back: this tile's offset inside bucket `tid`.  The status words of
+        // kWindow earlier tiles are read together; they are consumed newest
+        // first until a prefix is found, waiting only on words not yet published.
+        uint64_t excl = 0;
+        if (digit_owner && tile > 0) {
+            constexpr int kWindow = 2;
+            const uint64_t ready_tag = (uint64_t)(pass + 1);
+            int64_t t = tile - 1;
+            int spins = 0;
+            bool done = false;
+            while (!done) {
+                uint64_t v[kWindow];
+    #pragma unroll
+                for (int i = 0; i < kWindow; ++i)
+                    v[i] = t - i >= 0 ? __hip_atomic_load(&status[(t - i) * 256 + tid], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : 0ull;  // never consumed: tile 0 always holds a prefix
+    #pragma unroll
+                for (int i = 0; i < kWindow; ++i) {
+                    if (done) break;
+                    uint64_t x = v[i];
+                    while ((x >> 56) != ready_tag || (x & (kFlagAgg | kFlagPre)) == 0) {
+                        if (++spins > kSpinLimit) {  // cannot happen while every earlier tile runs; bail out loudly
+                            __hip_atomic_store(&ctl[kCtlError], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            x = ready_tag << 56 | kFlagPre;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        x = __hip_atomic_load(&status[(t - i) * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    excl += x & kCountMask;
+                    if (x & kFlagPre) done = true;
+                }
+                t -= kWindow;
+            }
+            __hip_atomic_store(&status[tile * 256 + tid], tag | kFlagPre | ((excl + cnt) & kCountMask),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-    }
-    const uint32_t lo = block_excl_scan<kSweepThreads>(cnt, s_wave);
-    if (digit_owner) {
-        s_lo[tid] = lo;
-        s_go[tid] = gbase[pass * 256 + tid] + (uint32_t)excl;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        const uint32_t dg = dp[r] & 255u;
-        dp[r] = (dp[r] >> 8) + s_lo[dg] + s_wrun[w][dg];  // slot in the ranked tile
-    }
-    __syncthreads();  // the counts are read; their storage becomes the staged keys
-    uint32_t vr[kSweepRounds];
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        const int li = w * kPerWave + r * kWave + lane;
-        vr[r] = li < m ? vs[base + li] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        if (w * kPerWave + r * kWave + lane < m) {
-            s_key[dp[r]] = kr[r];
-            s_val[dp[r]] = vr[r];
+        __syncthreads();  // every wave's counts are final
+        if (digit_owner) {
+            uint32_t acc = 0;
+    #pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                const uint32_t c = s_wrun[q][tid];
+                s_wrun[q][tid] = acc;
+                acc += c;
+            }
         }
-    }
-    __syncthreads();
-    // leave in digit order: consecutive slots of one digit are consecutive destinations
-#pragma unroll
-    for (int r = 0; r < kSweepRounds; ++r) {
-        const int j = r * kSweepThreads + tid;
-        if (j < m) {
-            const uint64_t key = s_key[j];
-            const uint32_t dg = digit(key);
-            const uint32_t pos = s_go[dg] + ((uint32_t)j - s_lo[dg]);
-            if (mode & kModeOut32)
-                reinterpret_cast<uint32_t *>(kd)[pos] = in32 ? (uint32_t)key : (uint32_t)((key - kbase) >> nshift);
-            else if (!(mode & kModeNoKeys))
-                kd[pos] = key;
-            vd[pos] = s_val[j];
+        const uint32_t lo = block_excl_scan<kSweepThreads>(cnt, s_wave);
+        if (digit_owner) {
+            s_lo[tid] = lo;
+            s_go[tid] = gbase[pass * 256 + tid] + (uint32_t)excl;
         }
+        __syncthreads();
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            const uint32_t dg = dp[r] & 255u;
+            dp[r] = (dp[r] >> 8) + s_lo[dg] + s_wrun[w][dg];  // slot in the ranked tile
+        }
+        __syncthreads();  // the counts are read; their storage becomes the staged keys
+        uint32_t vr[kSweepRounds];
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            const int li = w * kPerWave + r * kWave + lane;
+            vr[r] = li < m ? vs[base + li] : 0u;
+        }
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            if (w * kPerWave + r * kWave + lane < m) {
+                s_key[dp[r]] = kr[r];
+                s_val[dp[r]] = vr[r];
+            }
+        }
+        __syncthreads();
+        // leave in digit order: consecutive slots of one digit are consecutive destinations
+    #pragma unroll
+        for (int r = 0; r < kSweepRounds; ++r) {
+            const int j = r * kSweepThreads + tid;
+            if (j < m) {
+                const uint64_t key = s_key[j];
+                const uint32_t dg = digit(key);
+                const uint32_t pos = s_go[dg] + ((uint32_t)j - s_lo[dg]);
+                if (mode & kModeOut32)
+                    reinterpret_cast<uint32_t *>(kd)[pos] = in32 ? (uint32_t)key : (uint32_t)((key - kbase) >> nshift);
+                else if (!(mode & kModeNoKeys))
+                    kd[pos] = key;
+                vd[pos] = s_val[j];
+            }
+        }
+        if (!Persistent) break;
+        __syncthreads();  // the staged tile is written out before the next tile reuses LDS
     }
 }
 
@@ -460,15 +467,23 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
 }
 
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag,
-                     bool keep_keys) {
+                     bool keep_keys, bool sparse) {
     const bool main_sort = !tag || !tag[0];
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
     JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, keep_keys ? 1 : 0, b.ctl, b.gbase);
+    // A sparse sort's live count is far below its bound and known only on
+    // the device: its passes run persistent workgroups, at most the resident
+    // ones (three per compute unit), instead of one workgroup per possible
+    // tile.
+    const int64_t cap = (int64_t)device_cu_count() * 3;
+    const int64_t grid = tiles < cap ? tiles : cap;
     JB_LAUNCH_CHECK();
     for (int pass = 0; pass < 8; ++pass) {
-        JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups", main_sort ? k_onesweep<0> : k_onesweep<1>,
-                        dim3((unsigned)tiles), dim3(kSweepThreads), 0, st, b.keys[0], b.keys[1], b.vals[0], b.vals[1],
-                        n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.kmin, b.status, b.tile_ctr);
+        JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups",
+                        sparse ? (k_onesweep<1, true>) : main_sort ? (k_onesweep<0, false>) : (k_onesweep<1, false>),
+                        dim3((unsigned)(sparse ? grid : tiles)), dim3(kSweepThreads), 0, st, b.keys[0], b.keys[1],
+                        b.vals[0], b.vals[1], n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.kmin, b.status,
+                        b.tile_ctr);
         JB_LAUNCH_CHECK();
     }
     return JABBA_OK;

@@ -46,7 +46,7 @@ def timing_name(kernel: str) -> str:
     if base == "k_compress":
         return "k_compress_znorm" if ("true" in targs or "(bool)1" in targs) else "k_compress<W>"
     if base == "k_onesweep":
-        return base + ("_groups" if targs == "<1>" else "")
+        return base + ("_groups" if targs.startswith("<1") else "")
     if base in ("k_key", "k_gather"):
         return base + ("_pca" if targs == "<1>" else "")
     if base == "k_recon":
