@@ -173,13 +173,33 @@ __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__r
             if (lane == 0) cnt[s] = (series_off[s + 1] - series_off[s]) >= 1 ? 1 : 0;
             continue;
         }
+        // exact integer sum, so any order: four chunks' loads are issued
+        // before any is used (symbols, then their centers)
+        constexpr int kAhead = 4;
         u128 acc = 0;
         bool ok = true;
-        for (int64_t j = a + lane; j < b; j += kWave) {
-            u128 lt;
-            double it;
-            src.get(j, lt, it, ok);
-            acc += lt;
+        for (int64_t j0 = a + lane; j0 < b; j0 += kAhead * kWave) {
+            int32_t c[kAhead];
+            Src::Raw r[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int64_t j = j0 + (int64_t)u * kWave;
+                c[u] = j < b ? src.tag(j) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int64_t j = j0 + (int64_t)u * kWave;
+                r[u] = j < b ? src.load(j, c[u]) : Src::Raw{0.0, 0.0, 0, false};
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                if (j0 + (int64_t)u * kWave < b) {
+                    u128 lt;
+                    double it;
+                    src.convert(r[u], lt, it, ok);
+                    acc += lt;
+                }
+            }
         }
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) acc += xor_u128(acc, m);

@@ -112,8 +112,20 @@ __global__ __launch_bounds__(kThreads) void k_global_hist(const uint64_t *__rest
     const uint64_t k0 = *kmin;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         uint64_t k = keys[i] - k0;
+        const uint64_t active = __ballot(true);
+        const int leader = __ffsll((unsigned long long)active) - 1;
 #pragma unroll
-        for (int d = 0; d < 8; ++d) atomicAdd(&h[d][(k >> (8 * d)) & 255], 1u);
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t dg = (uint32_t)(k >> (8 * d)) & 255u;
+            // a digit the whole wavefront shares (the high digits mostly):
+            // one add of the lane count instead of colliding lane atomics
+            const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
+            if (__ballot(dg == first) == active) {
+                if (lane_id() == leader) atomicAdd(&h[d][first], (uint32_t)__popcll(active));
+            } else {
+                atomicAdd(&h[d][dg], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 8 * 256; i += kThreads) {
