@@ -233,6 +233,32 @@ def test_digitize_edge_cases(case):
     assert_centers_close(d, od, inc, od.symbols)
 
 
+@pytest.mark.parametrize("n", [200, 300, 700])
+def test_digitize_long_active_lists(n):
+    """Many live Stage I starts at once with separated length columns.  A
+    large scl makes x dominate the key, so the pieces of one length share a
+    key window while their y lie about alpha or more apart: most start their
+    own group and stay active, more than the 256 mirrored per wavefront (the
+    per-bucket chains are dropped and rebuilt).  Bit for bit against the
+    oracle, in one block and in blocks of 257."""
+    rng = np.random.default_rng(21)
+    ln = np.concatenate([np.full(n, 5), np.full(n, 6), np.full(n // 3, 7)]).astype(np.int32)
+    inc = np.concatenate([np.linspace(-1, 1, n), np.linspace(-1, 1, n) + 0.003, np.linspace(-1, 1, n // 3)])
+    order = rng.permutation(ln.size)
+    ln, inc = ln[order], inc[order]
+    alpha, scl = 0.005, 1000.0
+    for B in (1 << 20, 257):
+        say(f"digitize, long active lists: n={n} B={B}")
+        sym, d, st = gpu_digitize(ln, inc, alpha, scl, B)
+        assert st == 0
+        od = O.digitize(ln, inc, alpha, scl, B)
+        if B > ln.size:
+            assert od.n_starts > 256  # the premise: more live starts than the mirror holds
+        assert d["k"] == od.k
+        np.testing.assert_array_equal(sym, od.symbols)
+        np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
+
+
 def test_digitize_nonfinite_status():
     from paper_2401_00109_amd import _lib
     w, ol, oi, _ = _pieces(1)
