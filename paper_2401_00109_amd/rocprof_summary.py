@@ -3,6 +3,7 @@
     python -m paper_2401_00109_amd.rocprof_summary \\
         --trace <dir with *_kernel_stats.csv> --fetch <FETCH_SIZE counter csv> \\
         --write <WRITE_SIZE counter csv> --workload scale --command "<cmd>" --out profiles
+    python -m paper_2401_00109_amd.rocprof_summary --sq <SQ counter csvs> --command "<cmd>" --out profiles
 
 HBM traffic per dispatch comes from two counter runs (FETCH_SIZE, then
 WRITE_SIZE, in KiB per dispatch).  Each counter is scaled by what it reads
@@ -70,15 +71,64 @@ def calibration(per: dict) -> float | None:
     return CAL_BYTES / (sum(vals) / len(vals) * 1024.0)
 
 
+SQ_SHOWN = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
+            "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "SQ_INSTS_VALU", "SQ_INSTS_LDS",
+            "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"]
+
+
+def sq_table(args) -> int:
+    """Median per-dispatch SQ counters of the kernels with the most wave cycles
+    in total, with the share of wave cycles spent waiting and issuing VALU work."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in args.sq:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if "jabba" in r["Kernel_Name"]:
+                    per[timing_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+
+    def med(v):
+        v = sorted(v)
+        return v[len(v) // 2] if v else None
+
+    rows = sorted(per.items(), key=lambda kv: -sum(kv[1].get("SQ_WAVE_CYCLES", [])))[:10]
+    shown = [c for c in SQ_SHOWN if any(c in d for _, d in rows)]
+    lines = [f"# SQ counters of the largest kernels, workload `{args.workload}`", "",
+             f"Command: `{args.command}`", "",
+             f"Source hash of the kernels: `{source_hash()}`", "",
+             "Median over the kernel's dispatches (skipped radix passes included), summed over the device. "
+             "wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES, valu = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES.", "",
+             "| kernel | wait | valu | " + " | ".join(shown) + " |",
+             "|---|---|---|" + "---|" * len(shown)]
+    for name, d in rows:
+        m = {c: med(d.get(c, [])) for c in shown}
+        wc = m.get("SQ_WAVE_CYCLES")
+        wait = f"{m['SQ_WAIT_ANY'] / wc:.2f}" if wc and m.get("SQ_WAIT_ANY") is not None else ""
+        valu = f"{m['SQ_ACTIVE_INST_VALU'] / wc:.2f}" if wc and m.get("SQ_ACTIVE_INST_VALU") is not None else ""
+        lines.append(f"| {name} | {wait} | {valu} | " +
+                     " | ".join("" if m[c] is None else f"{m[c]:.3g}" for c in shown) + " |")
+    path = os.path.join(args.out, f"sq_counters_{args.workload}.md")
+    os.makedirs(args.out, exist_ok=True)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--sq", nargs="*", default=None,
+                    help="counter-collection csvs of SQ counter runs: writes sq_counters_<workload>.md instead")
     ap.add_argument("--workload", default="scale")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", default="profiles")
     args = ap.parse_args()
+    if args.sq:
+        return sq_table(args)
+    if not args.trace or not args.fetch or not args.write:
+        ap.error("--trace, --fetch and --write are required without --sq")
 
     stats_csv = glob.glob(os.path.join(args.trace, "*kernel_stats.csv"))[0]
     with open(stats_csv) as fh:
