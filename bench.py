@@ -88,6 +88,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-series", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop latency measurement")
+    ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay (profiler runs)")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain 1 GiB copy kernel (for rocprofv3 counter scaling)")
@@ -307,6 +309,33 @@ def main() -> int:
         torch.cuda.synchronize()
         log("calibration copy kernel: 3 x neg over 1 GiB (read 1 GiB, write 1 GiB per launch)")
 
+    # ---------------------------------------------------------------- serving latency (not in the step)
+    # The metric's p99 part: the serving loop with the same resident
+    # dictionary, saturation from a closed loop, then Poisson arrivals at half
+    # of it; latency is arrival to symbols on the host (H2D and D2H included).
+    serving = None
+    if not args.no_serving:
+        from paper_2401_00109_amd.inputs import request_stream
+        from paper_2401_00109_amd.serve import Server, summarize
+        srv = Server(resident, slots=4, max_series=256, device=dev)
+        srv.run(request_stream(1, 20, 0.0, max_series=256, first_id=10_000_000), realtime=False)
+        closed = request_stream(2, args.serving_requests, 0.0, max_series=256, first_id=20_000_000)
+        t = time.perf_counter()
+        res = srv.run(closed, realtime=False)
+        sat = len(res) / (time.perf_counter() - t)
+        reqs = request_stream(3, args.serving_requests, 0.5 * sat, max_series=256, first_id=30_000_000)
+        t = time.perf_counter()
+        res = srv.run(reqs, realtime=True)
+        sm = summarize(res, time.perf_counter() - t)
+        serving = {"saturation_req_per_s": round(sat, 1), "rate_req_per_s": round(0.5 * sat, 1),
+                   "requests": sm["requests"], "p50_ms": round(sm["p50_ms"], 3), "p99_ms": round(sm["p99_ms"], 3),
+                   "points_per_s": round(sm["points_per_s"], 1),
+                   "requests_shape": "1-256 random walks of 500-50,000 points, four slots",
+                   "latency": "arrival to symbols on the host, H2D and D2H included"}
+        log(f"serving: saturation {sat:.0f} req/s; at half of it p50 {sm['p50_ms']:.2f} ms, "
+            f"p99 {sm['p99_ms']:.2f} ms")
+        del srv
+
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None
     if not args.no_cpu_baseline:
@@ -341,6 +370,7 @@ def main() -> int:
         "roofline": roofline,
         "dominant_kernel_with_batches_in_flight": in_flight,
         "batched_vs_plain": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
         "reconstruction_mse": rec.mse(),
         "digitization_quality": quality,
