@@ -441,7 +441,9 @@ int jabba_fp64_selftest(const double *a, const double *b, double *quot, double *
 /*
  * Per-kernel timing for benchmarks.  While enabled, every kernel launch of
  * the library is bracketed by two HIP events recorded on the stream the
- * kernel is launched on; durations accumulate per kernel name.  Enabling
+ * kernel is launched on; durations accumulate per kernel name.  The eight
+ * radix passes of a sort run back to back and are bracketed together (one
+ * event pair, counted as eight launches).  Enabling
  * clears the accumulators.  Must be off while a plan is being captured.
  * jabba_timing_get synchronises on the recorded events; *launches is the
  * number of timed launches of `name` (0 if none).  jabba_timing_names writes

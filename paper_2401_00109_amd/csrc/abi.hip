@@ -12,10 +12,14 @@
 namespace jabba {
 
 namespace {
+struct Pending {
+    hipEvent_t a, b;
+    int launches;
+};
 struct TimingSlot {
     double ms = 0.0;
     int64_t launches = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<Pending> pending;
 };
 std::atomic<bool> g_timing{false};
 std::mutex g_tmu;
@@ -45,18 +49,19 @@ std::string clean_name(const char *n) {
 void settle(TimingSlot &t) {
     for (auto &pr : t.pending) {
         float ms = 0.0f;
-        if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        if (hipEventSynchronize(pr.b) == hipSuccess && hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) {
             t.ms += ms;
-            t.launches += 1;
+            t.launches += pr.launches;
         }
-        g_pool.push_back(pr.first);
-        g_pool.push_back(pr.second);
+        g_pool.push_back(pr.a);
+        g_pool.push_back(pr.b);
     }
     t.pending.clear();
 }
 }  // namespace
 
-KernelTimer::KernelTimer(const char *name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
+KernelTimer::KernelTimer(const char *name, hipStream_t st, int launches)
+    : name_(name), st_(st), a_(nullptr), launches_(launches) {
     if (!g_timing.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> g(g_tmu);
     hipEvent_t e = ev_get();
@@ -68,7 +73,7 @@ KernelTimer::~KernelTimer() {
     std::lock_guard<std::mutex> g(g_tmu);
     hipEvent_t e = ev_get();
     if (e && hipEventRecord(e, st_) == hipSuccess)
-        g_slots[clean_name(name_)].pending.emplace_back((hipEvent_t)a_, e);
+        g_slots[clean_name(name_)].pending.push_back(Pending{(hipEvent_t)a_, e, launches_});
     else
         g_pool.push_back((hipEvent_t)a_);
 }

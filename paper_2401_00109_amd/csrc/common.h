@@ -57,12 +57,15 @@ int device_cu_count();
 
 // Opt-in per-kernel event timing (jabba_timing_*): a scope that records an
 // event on `st` when created and another when destroyed, if timing is on.
+// Times the launches enqueued during its lifetime on one stream as `launches`
+// launches of `name` (one event pair around them all).
 struct KernelTimer {
-    KernelTimer(const char *name, hipStream_t st);
+    KernelTimer(const char *name, hipStream_t st, int launches = 1);
     ~KernelTimer();
     const char *name_;
     hipStream_t st_;
     void *a_;
+    int launches_;
 };
 // Launch with the optional event timing around it (the kernel expression's
 // text is the timing name).

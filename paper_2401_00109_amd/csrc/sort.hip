@@ -490,12 +490,14 @@ int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, 
     const int64_t cap = (int64_t)device_cu_count() * 3;
     const int64_t grid = tiles < cap ? tiles : cap;
     JB_LAUNCH_CHECK();
+    // the eight passes run back to back and are timed as one group of eight
+    // launches, so the per-launch figure carries no event of its own
+    KernelTimer timer(main_sort ? "k_onesweep" : "k_onesweep_groups", st, 8);
     for (int pass = 0; pass < 8; ++pass) {
-        JB_LAUNCH_NAMED(main_sort ? "k_onesweep" : "k_onesweep_groups",
-                        sparse ? (k_onesweep<1, true>) : main_sort ? (k_onesweep<0, false>) : (k_onesweep<1, false>),
-                        dim3((unsigned)(sparse ? grid : tiles)), dim3(kSweepThreads), 0, st, b.keys[0], b.keys[1],
-                        b.vals[0], b.vals[1], n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.kmin, b.status,
-                        b.tile_ctr);
+        hipLaunchKernelGGL(sparse ? (k_onesweep<1, true>) : main_sort ? (k_onesweep<0, false>) : (k_onesweep<1, false>),
+                           dim3((unsigned)(sparse ? grid : tiles)), dim3(kSweepThreads), 0, st, b.keys[0], b.keys[1],
+                           b.vals[0], b.vals[1], n_dev, n_max, 8 * pass, b.ctl, pass, b.gbase, b.kmin, b.status,
+                           b.tile_ctr);
         JB_LAUNCH_CHECK();
     }
     return JABBA_OK;
