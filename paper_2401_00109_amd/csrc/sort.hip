@@ -9,14 +9,15 @@
 // the tile's digits, and finds the tile's offset inside each digit bucket by
 // decoupled look-back over the earlier tiles' published counts (each status
 // word carries the pass tag, an aggregate/prefix flag and the count).  Inside
-// a tile each wavefront ranks its own contiguous quarter in index order
-// (peers with the same digit by eight ballots, a running count per digit in
-// the wave's LDS row), and the quarters are ordered by per-digit offsets; the
+// a tile each wavefront ranks its own contiguous slice in index order (peers
+// with the same digit by eight ballots, a running count per digit in the
+// wave's LDS row), and the slices are ordered by per-digit offsets; the
 // ranked tile is staged in LDS and leaves in digit order, so each digit's run
-// of the tile is one contiguous, coalesced stretch of the destination.  A digit that is the
-// same for every key is skipped; the decision and the buffer parity of every
-// pass are taken on the device from the global histograms, so no host
-// read-back is needed and the sort can be captured in a HIP graph.
+// of the tile is one contiguous, coalesced stretch of the destination.  A
+// digit that is the same for every key is skipped; the decision and the
+// buffer parity of every pass are taken on the device from the global
+// histograms, so no host read-back is needed and the sort can be captured in
+// a HIP graph.
 //
 // A sort whose caller needs only the order (not the sorted keys) carries
 // less: once the digits not yet sorted fit in 32 bits, the passes read and

@@ -28,13 +28,21 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CAL_BYTES = float(1 << 30)
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and with whitespace collapsed, so that an
+    edit of comments alone leaves the hash (and the measurements) valid."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash() -> str:
-    """Hash of the HIP sources; identifies the kernels a measurement belongs to."""
+    """Hash of the HIP sources' code; identifies the kernels a measurement belongs to."""
     h = hashlib.sha256()
     d = os.path.join(PKG, "csrc")
     for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            h.update(f.encode() + _code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
