@@ -191,11 +191,9 @@ struct SortBuffers {
 size_t sort_workspace(int64_t n_max, Carve &c, SortBuffers *b);
 // Resets the control words and the global digit histograms.
 int radix_sort_init(const SortBuffers &b, hipStream_t st);
-// ctl[kSortCtlMode + d]: the key widths pass d of the last sort moved.
+// ctl[kSortCtlMode + d]: the key widths (kSortMode* bits of sort_plan.h)
+// pass d of the last sort moved.
 constexpr int kSortCtlMode = 40;
-constexpr int kSortModeIn32 = 1;    // read 32-bit keys
-constexpr int kSortModeOut32 = 2;   // wrote 32-bit keys
-constexpr int kSortModeNoKeys = 4;  // wrote no keys (order only)
 
 // Global histograms of the eight digits of keys[0] (after the keys are written).
 int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);

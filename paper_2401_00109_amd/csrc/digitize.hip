@@ -16,6 +16,7 @@
 // Decisions use binary64 with no contraction, in the order of the sequential
 // definition, so local starts, blocks and symbols are bit-identical to it.
 #include "common.h"
+#include "sort_plan.h"
 
 namespace jabba {
 
@@ -313,10 +314,8 @@ __global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds, double 
         int64_t act = 0, bytes = 0;
         for (int d = 0; d < 8; ++d) {
             if (ctl[1 + d]) continue;
-            const int mode = ctl[kSortCtlMode + d];
             act += 1;
-            bytes += ((mode & kSortModeIn32) ? 4 : 8) + 4 +
-                     ((mode & kSortModeNoKeys) ? 0 : (mode & kSortModeOut32) ? 4 : 8) + 4;
+            bytes += sort_pass_bytes(ctl[kSortCtlMode + d]);
         }
         ds->sort_passes = act;
         ds->sort_bytes = bytes;

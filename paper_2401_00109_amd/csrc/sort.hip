@@ -24,6 +24,7 @@
 // write 32-bit keys (key - kmin shifted past the sorted digits), and the last
 // pass writes the values alone.
 #include "common.h"
+#include "sort_plan.h"
 
 namespace jabba {
 
@@ -179,30 +180,10 @@ __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ 
     }
     if (threadIdx.x == 0) {
         ctl[kCtlFinal] = active & 1;
-        // key - kmin is 0 on the smallest key, so a skipped digit is 0 in
-        // every key; digits above the highest active one can be dropped
-        int top = -1;
-        for (int d = 0; d < 8; ++d)
-            if (!ctl[kCtlSkip + d]) top = d;
-        bool narrow = false;
-        int base = 0;
-        for (int d = 0; d < 8; ++d) {
-            int mode = 0;
-            if (!ctl[kCtlSkip + d] && !keep_keys) {
-                mode = narrow ? kModeIn32 : 0;
-                if (d == top) {
-                    mode |= kModeNoKeys;
-                } else if (narrow) {
-                    mode |= kModeOut32;
-                } else if (top - d <= 4) {  // digits d+1..top fit in 32 bits
-                    mode |= kModeOut32;
-                    narrow = true;
-                    base = 8 * (d + 1);
-                }
-            }
-            ctl[kCtlMode + d] = mode;
-        }
-        ctl[kCtlBase] = base;
+        int skip[8], modes[8];
+        for (int d = 0; d < 8; ++d) skip[d] = ctl[kCtlSkip + d];
+        ctl[kCtlBase] = sort_pass_modes(skip, keep_keys != 0, modes);
+        for (int d = 0; d < 8; ++d) ctl[kCtlMode + d] = modes[d];
     }
 }
 
