@@ -419,6 +419,44 @@ def test_full_size_scale_workload(full_scale):
     say(f"  digitize parity ok: k={od.k} G={od.n_starts} center_inc worst rel {worst:.3e}")
 
 
+@pytest.mark.parametrize("n_sets", [1, 2])
+def test_pipeline_small(n_sets):
+    """Batches in flight on a small scale workload (41 series): one and two
+    buffer sets, round robin and one batch at a time; every set's symbols,
+    encodings and reconstruction equal a plain single-stream run's, and the
+    symbols the oracle's."""
+    import paper_2401_00109_amd as J
+    from paper_2401_00109_amd.pipeline import Pipeline
+    from paper_2401_00109_amd.serve import build_resident_dictionary
+    T = torch()
+    w = _workload(2)
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    od = O.digitize(ol, oi, w.alpha, w.scl, w.B)
+    N = ol.size
+    v, so = to_dev(w.values), to_dev(w.series_off)
+    t0h = np.where(np.diff(w.series_off) > 0, w.values[np.minimum(w.series_off[:-1], max(w.n_points - 1, 0))], 0.0)
+    resident = build_resident_dictionary(DEV)
+    say(f"pipeline, {n_sets} set(s), {N} pieces")
+    pipe = Pipeline(v, so, to_dev(t0h), w.D, w.tol, w.alpha, w.scl, w.B, N, resident, n_sets=n_sets)
+    ref = None
+    for pipelined in (True, False):
+        pipe.run(3 * n_sets, pipelined=pipelined)
+        T.cuda.synchronize()
+        for S in pipe.sets:
+            assert S.sz.status() == (0, 0)
+            np.testing.assert_array_equal(S.sz.symbols[:N].cpu().numpy(), od.symbols)
+            got = (S.enc[:N].cpu().numpy(), S.rec.out_off.cpu().numpy(),
+                   S.rec.out[: int(S.rec.out_off[-1].item())].cpu().numpy())
+            if ref is None:
+                enc = J.encode(S.pieces.len, S.pieces.inc, S.pieces.n_pieces, N, resident)
+                r = J.reconstruct(S.sz.symbols, S.pieces.piece_off, so, to_dev(t0h), S.sz.dictionary)
+                T.cuda.synchronize()
+                ref = (enc[:N].cpu().numpy(), r["out_off"].cpu().numpy(), r["out"].cpu().numpy())
+            np.testing.assert_array_equal(got[0], ref[0])
+            np.testing.assert_array_equal(got[1], ref[1])
+            np.testing.assert_array_equal(got[2].view(np.uint64), ref[2].view(np.uint64))
+
+
 def test_full_size_pipelined_step(full_scale):
     """The benchmark's timed configuration: three buffer sets on three
     streams, each step compress, encode against the resident dictionary,
