@@ -210,9 +210,11 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wave
 // below 256 own one digit each (histogram, look-back, bucket bases).  The
 // per-wave digit counts and the tile histogram share LDS with the staged
 // keys (they are dead before the tile is staged), and the values are loaded
-// only for the staging, after the look-back: 51 KB of LDS and at most 80
+// only for the staging, after the look-back: 50 KB of LDS and at most 80
 // registers let three workgroups share a compute unit, so one tile's
-// look-back and loads overlap the others' work.
+// look-back and loads overlap the others' work.  Each element finds its slot
+// with one LDS read (per-wave offsets that start at the digit's local start)
+// and its destination with one more (a per-digit distance).
 constexpr int kSweepThreads = 512;
 constexpr int kSweepRounds = kTileN / kSweepThreads;
 constexpr int kSweepWavesPerSimd = 6;
@@ -234,8 +236,7 @@ __global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
     } s_u;
     static_assert(sizeof(s_u.rank) <= sizeof(s_u.key), "ranking state must fit the staging buffer");
     __shared__ uint32_t s_val[kTileN];
-    __shared__ uint32_t s_lo[256];  // local start per digit
-    __shared__ uint32_t s_go[256];  // destination start per digit
+    __shared__ uint32_t s_delta[256];  // destination start minus local start, per digit
     __shared__ uint32_t s_wave[kWaves];
     uint32_t *const s_hist = s_u.rank.hist;
     uint32_t (*const s_wrun)[256] = s_u.rank.wrun;
@@ -359,25 +360,24 @@ __global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();  // every wave's counts are final
+        const uint32_t lo = block_excl_scan<kSweepThreads>(cnt, s_wave);
         if (digit_owner) {
-            uint32_t acc = 0;
+            // per-wave offsets that start at the digit's local start, and the
+            // distance from a staged slot to its destination
+            uint32_t acc = lo;
     #pragma unroll
             for (int q = 0; q < kWaves; ++q) {
                 const uint32_t c = s_wrun[q][tid];
                 s_wrun[q][tid] = acc;
                 acc += c;
             }
-        }
-        const uint32_t lo = block_excl_scan<kSweepThreads>(cnt, s_wave);
-        if (digit_owner) {
-            s_lo[tid] = lo;
-            s_go[tid] = gbase[pass * 256 + tid] + (uint32_t)excl;
+            s_delta[tid] = gbase[pass * 256 + tid] + (uint32_t)excl - lo;
         }
         __syncthreads();
     #pragma unroll
         for (int r = 0; r < kSweepRounds; ++r) {
             const uint32_t dg = dp[r] & 255u;
-            dp[r] = (dp[r] >> 8) + s_lo[dg] + s_wrun[w][dg];  // slot in the ranked tile
+            dp[r] = (dp[r] >> 8) + s_wrun[w][dg];  // slot in the ranked tile
         }
         __syncthreads();  // the counts are read; their storage becomes the staged keys
         uint32_t vr[kSweepRounds];
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
             if (j < m) {
                 const uint64_t key = s_key[j];
                 const uint32_t dg = digit(key);
-                const uint32_t pos = s_go[dg] + ((uint32_t)j - s_lo[dg]);
+                const uint32_t pos = s_delta[dg] + (uint32_t)j;
                 if (mode & kModeOut32)
                     reinterpret_cast<uint32_t *>(kd)[pos] = in32 ? (uint32_t)key : (uint32_t)((key - kbase) >> nshift);
                 else if (!(mode & kModeNoKeys))
