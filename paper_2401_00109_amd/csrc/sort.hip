@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kSweepThreads, kSweepWavesPerSimd) void k_onesweep(
         // first until a prefix is found, waiting only on words not yet published.
         uint64_t excl = 0;
         if (digit_owner && tile > 0) {
-            constexpr int kWindow = 2;
+            constexpr int kWindow = 4;
             const uint64_t ready_tag = (uint64_t)(pass + 1);
             int64_t t = tile - 1;
             int spins = 0;
