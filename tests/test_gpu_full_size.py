@@ -1,101 +1,181 @@
 """Full-size parity for the uneven workload (50,000 series of log-uniform
-length, 7.2e8 points) and the multivariate one (1,024 samples x 64 channels
-of 5,000 points, 3.3e8 points), in the launch configuration the benchmark
-uses at these sizes: one Symbolizer on the default stream.
+length, 7.2e8 points, 3.0e8 pieces) and the multivariate one (1,024 samples x
+64 channels of 5,000 points, 3.3e8 points), in the launch configuration the
+benchmark uses at these sizes: one Symbolizer on the default stream.
 
-The oracle's global digitization of 1.5e8-3e8 pieces would take minutes, so
-the digitization is checked through what holds at any size, each against an
-independent host computation:
-  * sigma_len and sigma_inc equal the oracle's scaling of the same pieces;
-  * counts are the symbol histogram and center_len the exact member mean
-    (an integer sum divided once), bit for bit;
-  * every symbol's scaled members lie within 2 alpha of one point (a member
-    is within alpha of its Stage I start, which is within alpha of its
-    global start), so the mean squared distance to the center is at most
-    4 alpha^2 per symbol.
-Compression and reconstruction are per series: sampled series are compared
-with the oracle bit for bit (pieces, reconstructed points, offsets), the
-squared error within rtol 1e-12.
+Everything is compared with the oracle element by element over the whole
+workload: every piece (len, inc) and piece offset; sigma_len and sigma_inc;
+the Stage I starting-point count; k and every symbol; counts, center lengths
+and cx bit for bit, center increments and cy within the 1e-12 bar; and every
+reconstructed point, reconstructed on both sides from the oracle's
+dictionary.  The oracle runs step by step (tests/oracle_full.py: the
+oracle's own step functions, independent parts spread over threads), one
+test per step, so each test reports within a minute or two.  As an extra
+check that needs no oracle, every symbol's mean squared distance of its
+members to its center is at most 4 alpha^2 (a member is within alpha of
+its Stage I start, and that start within alpha of its global start).
 """
+import time
+
 import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import say, to_dev, torch
-from paper_2401_00109_amd.inputs import make_workload, pack
+import oracle_full as F
+from gpu_util import DEV, assert_centers_close, say, to_dev, torch
+from paper_2401_00109_amd.inputs import make_workload
 
 pytestmark = pytest.mark.gpu
 
-
-def _sample(n_series, k=64):
-    rng = np.random.default_rng(11)
-    idx = np.concatenate([np.arange(16), np.arange(n_series - 16, n_series),
-                          rng.choice(n_series, k - 32, replace=False)])
-    return np.unique(idx[(idx >= 0) & (idx < n_series)])
+_state: dict = {}
 
 
-@pytest.mark.timeout(600)
-@pytest.mark.parametrize("wid", [3, 4])
-def test_full_size_workload(wid):
-    import paper_2401_00109_amd as J
-    T = torch()
-    w = make_workload(wid, seed=0)
-    say(f"full-size workload {w.name}: {w.n_series} series, {w.n_points} points")
-    v, so = to_dev(w.values), to_dev(w.series_off)
-    sz = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B, max_len=w.max_len)
-    sz.run(v, so)
-    T.cuda.synchronize()
-    assert sz.status() == (0, 0)
-    ln, inc, po = sz.pieces.host()
-    N = ln.size
-    sym = sz.symbols[:N].cpu().numpy()
-    d = sz.dictionary.host()
-    k = d["k"]
-    say(f"  N={N} pieces, k={k} symbols")
+def _rss_gb() -> float:
+    import resource
+    return resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1e6
 
-    # compression, sampled series against the oracle
-    idx = _sample(w.n_series)
-    sub = [w.values[w.series_off[s]:w.series_off[s + 1]] for s in idx]
-    sv, soff = pack(sub)
-    ol, oi, opo = O.compress(sv, soff, w.D, w.tol, w.max_len)
-    gl = np.concatenate([ln[po[s]:po[s + 1]] for s in idx])
-    gi = np.concatenate([inc[po[s]:po[s + 1]] for s in idx])
-    np.testing.assert_array_equal(np.diff(opo), po[idx + 1] - po[idx])
-    np.testing.assert_array_equal(gl, ol)
-    np.testing.assert_array_equal(gi.view(np.uint64), oi.view(np.uint64))
-    say(f"  compress: {idx.size} sampled series ({ol.size} pieces) equal the oracle's")
 
-    # digitization, properties at full size
-    sl, si, x, y, _ = O.scaling(ln, inc, w.scl)
-    assert (d["sigma_len"], d["sigma_inc"]) == (sl, si)
-    assert sym.min() >= 0 and sym.max() < k
-    cnt = np.bincount(sym, minlength=k)
-    np.testing.assert_array_equal(d["count"], cnt)
-    assert cnt.min() >= 1
-    mean_len = np.bincount(sym, weights=ln.astype(np.float64), minlength=k) / cnt
-    np.testing.assert_array_equal(d["center_len"].view(np.uint64), mean_len.view(np.uint64))
-    cx = w.scl * (mean_len / sl)
-    cy = d["center_inc"] / si
-    dev2 = (x - cx[sym]) ** 2 + (y - cy[sym]) ** 2
-    del x, y
-    per = np.bincount(sym, weights=dev2, minlength=k) / cnt
-    del dev2
-    assert per.max() <= 4.0 * w.alpha ** 2 * (1 + 1e-9), per.max()
-    say(f"  digitize: scaling, counts, center lengths exact; worst symbol mean squared spread "
-        f"{per.max():.3e} <= 4 alpha^2 = {4 * w.alpha ** 2:.3e}")
+class _FullSize:
+    wid = 0
 
-    # reconstruction, sampled series against the oracle (same dictionary)
-    t0 = np.where(np.diff(w.series_off) > 0, w.values[np.minimum(w.series_off[:-1], max(w.n_points - 1, 0))], 0.0)
-    r = J.reconstruct(sz.symbols, sz.pieces.piece_off, so, to_dev(t0), sz.dictionary, values=v)
-    T.cuda.synchronize()
-    assert r["status"] == 0
-    out_off = r["out_off"].cpu().numpy()
-    ssym = np.concatenate([sym[po[s]:po[s + 1]] for s in idx])
-    spo = np.concatenate([[0], np.cumsum(po[idx + 1] - po[idx])])
-    out, oo, _, sse, cnt_e = O.reconstruct(ssym, spo, soff, t0[idx], d["center_len"], d["center_inc"], orig=sv)
-    gout = np.concatenate([r["out"][out_off[s]:out_off[s + 1]].cpu().numpy() for s in idx])
-    np.testing.assert_array_equal(np.diff(oo), out_off[idx + 1] - out_off[idx])
-    np.testing.assert_array_equal(gout.view(np.uint64), out.view(np.uint64))
-    np.testing.assert_array_equal(r["cnt"].cpu().numpy()[idx], cnt_e)
-    np.testing.assert_allclose(r["sse"].cpu().numpy()[idx], sse, rtol=1e-12, atol=1e-300)
-    say(f"  reconstruct: {idx.size} sampled series ({out.size} points) equal the oracle's")
+    def _s(self):
+        st = _state.get(self.wid)
+        if st is None:
+            pytest.skip("the device run of this workload did not complete")
+        return st
+
+    @pytest.mark.timeout(400)
+    def test_1_device_run(self):
+        import paper_2401_00109_amd as J
+        T = torch()
+        _state.clear()
+        t = time.time()
+        w = make_workload(self.wid, seed=0)
+        say(f"full-size workload {w.name}: {w.n_series} series, {w.n_points} points (generated in "
+            f"{time.time() - t:.0f} s)")
+        v, so = to_dev(w.values), to_dev(w.series_off)
+        sz = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B, max_len=w.max_len)
+        sz.run(v, so)
+        T.cuda.synchronize()
+        assert sz.status() == (0, 0)
+        ln, inc, po = sz.pieces.host()
+        N = ln.size
+        stats = sz.stats()
+        st = {"w": w, "ln": ln, "inc": inc, "po": po, "sym": sz.symbols[:N].cpu().numpy(),
+              "dict": sz.dictionary.host(), "stats": stats}
+        del sz, v, so
+        T.cuda.empty_cache()
+        _state[self.wid] = st
+        say(f"  device: N={N} pieces, G={stats['G']} starting points, k={stats['k']} symbols; "
+            f"host RSS {_rss_gb():.1f} GB")
+
+    @pytest.mark.timeout(400)
+    def test_2_compress(self):
+        st = self._s()
+        w = st["w"]
+        t = time.time()
+        ol, oi, opo = F.compress(w.values, w.series_off, w.D, w.tol, w.max_len)
+        say(f"  oracle compress of all {w.n_series} series: {time.time() - t:.0f} s")
+        np.testing.assert_array_equal(opo, st["po"])
+        np.testing.assert_array_equal(ol, st["ln"])
+        np.testing.assert_array_equal(oi.view(np.uint64), st["inc"].view(np.uint64))
+        del st["ln"], st["inc"]
+        st["opo"] = opo
+        st["dig"] = F.Digitization(ol, oi, w.alpha, w.scl, w.B)
+        say(f"  compress: all {ol.size} pieces and {opo.size} offsets equal the oracle's")
+
+    @pytest.mark.timeout(400)
+    def test_3_scaling_and_sort(self):
+        st = self._s()
+        dig = st["dig"]
+        t = time.time()
+        dig.scaling()
+        d = st["dict"]
+        assert (d["sigma_len"], d["sigma_inc"]) == (dig.sigma_len, dig.sigma_inc)
+        dig.sort()
+        say(f"  oracle scaling and global sort of {dig.N} pieces: {time.time() - t:.0f} s; sigmas equal")
+
+    @pytest.mark.timeout(400)
+    def test_4_stage1(self):
+        st = self._s()
+        dig = st["dig"]
+        t = time.time()
+        dig.stage1()
+        say(f"  oracle Stage I over {dig.bstart.size - 1} blocks: {time.time() - t:.0f} s, G={dig.G}")
+        assert dig.G == st["stats"]["G"]
+
+    @pytest.mark.timeout(400)
+    def test_5_stage2_and_symbols(self):
+        st = self._s()
+        dig = st["dig"]
+        t = time.time()
+        dig.stage2()
+        say(f"  oracle Stage II and propagation: {time.time() - t:.0f} s, k={dig.k}")
+        assert dig.k == st["dict"]["k"] == st["stats"]["k"]
+        np.testing.assert_array_equal(st["sym"], dig.symbols)
+        say(f"  all {dig.N} symbols equal the oracle's")
+
+    @pytest.mark.timeout(400)
+    def test_6_centers(self):
+        st = self._s()
+        dig, d, w = st["dig"], st["dict"], st["w"]
+        t = time.time()
+        dig.centers()
+        say(f"  oracle dictionary of {dig.k} symbols: {time.time() - t:.0f} s")
+        np.testing.assert_array_equal(d["count"], dig.count)
+        np.testing.assert_array_equal(d["center_len"].view(np.uint64), dig.center_len.view(np.uint64))
+        np.testing.assert_array_equal(d["cx"].view(np.uint64), dig.cx.view(np.uint64))
+
+        class _R:  # the oracle's dictionary in the shape assert_centers_close reads
+            k, center_inc, cy, sigma_inc = dig.k, dig.center_inc, dig.cy, dig.sigma_inc
+
+        worst = assert_centers_close(d, _R, dig.inc, dig.symbols)
+        # the spread bound, from the oracle's scaling of the pieces and the device's centers
+        _, _, x, y, _ = O.scaling(dig.len, dig.inc, w.scl)
+        sym = dig.symbols
+        cnt = dig.count.astype(np.float64)
+        dev2 = (x - d["cx"][sym]) ** 2 + (y - d["cy"][sym]) ** 2
+        del x, y
+        per = np.bincount(sym, weights=dev2, minlength=dig.k) / cnt
+        del dev2
+        assert per.max() <= 4.0 * w.alpha ** 2 * (1 + 1e-9), per.max()
+        say(f"  dictionary: counts, center_len, cx exact; center_inc within {worst:.1e} relative; worst symbol "
+            f"spread {per.max():.3e} <= 4 alpha^2 = {4 * w.alpha ** 2:.3e}")
+
+    @pytest.mark.timeout(400)
+    def test_7_reconstruct(self):
+        import paper_2401_00109_amd as J
+        T = torch()
+        st = self._s()
+        dig, w = st["dig"], st["w"]
+        t0 = np.where(np.diff(w.series_off) > 0, w.values[np.minimum(w.series_off[:-1], max(w.n_points - 1, 0))],
+                      0.0)
+        od = J.Dictionary.from_host(dig.sigma_len, dig.sigma_inc, w.scl, w.alpha, dig.center_len, dig.center_inc,
+                                    dig.cx, dig.cy, dig.count, device=DEV)
+        v, so = to_dev(w.values), to_dev(w.series_off)
+        r = J.reconstruct(to_dev(st["sym"]), to_dev(st["opo"]), so, to_dev(t0), od, values=v)
+        T.cuda.synchronize()
+        assert r["status"] == 0
+        g_off = r["out_off"].cpu().numpy()
+        g_out = r["out"].cpu().numpy()
+        g_sse, g_cnt = r["sse"].cpu().numpy(), r["cnt"].cpu().numpy()
+        del r, v, so, od
+        T.cuda.empty_cache()
+        t = time.time()
+        out, oo, sse, cnt = F.reconstruct(dig.symbols, st["opo"], w.series_off, t0, dig.center_len, dig.center_inc,
+                                          w.values)
+        say(f"  oracle reconstruction of {out.size} points: {time.time() - t:.0f} s")
+        np.testing.assert_array_equal(g_off, oo)
+        np.testing.assert_array_equal(g_out.view(np.uint64), out.view(np.uint64))
+        np.testing.assert_array_equal(g_cnt[: w.n_series], cnt)
+        np.testing.assert_allclose(g_sse[: w.n_series], sse, rtol=1e-12, atol=1e-300)
+        say(f"  reconstruct: all {out.size} points equal the oracle's; host RSS {_rss_gb():.1f} GB")
+        _state.clear()
+
+
+class TestUneven(_FullSize):
+    wid = 3
+
+
+class TestMultivar(_FullSize):
+    wid = 4
