@@ -60,7 +60,8 @@ enum jabba_status {
     JABBA_ECAPACITY = -4,   /* device: more symbols than the dictionary capacity         */
     JABBA_ENONFINITE = -5,  /* device: a series value is NaN or infinite                 */
     JABBA_EOVERFLOW = -6,   /* a count exceeds the 2^31 limit                            */
-    JABBA_ENODEV = -7       /* no gfx950 device is current                               */
+    JABBA_ENODEV = -7,      /* no gfx950 device is current                               */
+    JABBA_ELIMIT = -8       /* a size exceeds the fixed maximum of an allocation-free call */
 };
 
 /* Library ABI version (JABBA_ABI_VERSION of the build). */
@@ -337,6 +338,31 @@ int jabba_encode_workspace(int64_t capacity, size_t *bytes);
  */
 int jabba_encode(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
                  const jabba_dict *dict, int32_t *symbols, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Largest dictionary capacity jabba_encode_noalloc accepts.  Its scratch is a
+ * fixed 3 MiB device array per GPU (jabba_encode_workspace of this capacity
+ * fits in it).
+ */
+#define JABBA_ENCODE_NOALLOC_MAX_CAPACITY 65536
+
+/*
+ * jabba_encode without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops that
+ * forbid allocation, harnesses that ban hipMalloc.  Same arguments, result
+ * and errors as jabba_encode, bit for bit.  The call allocates nothing: its
+ * scratch (the ordered centers and columns) is a file-scope device array of
+ * the library, one per GPU, resolved on the first call on each device and
+ * kept until the process ends.
+ *   dict->capacity > JABBA_ENCODE_NOALLOC_MAX_CAPACITY -> JABBA_ELIMIT,
+ *   nothing enqueued.
+ * Every call on one GPU shares that GPU's scratch, which holds the last
+ * call's contents (each call rewrites all it reads): calls that overlap on
+ * one GPU (different streams, or different host threads) race and must be
+ * serialised by the caller.
+ */
+int jabba_encode_noalloc(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                         const jabba_dict *dict, int32_t *symbols, void *stream);
 
 /*
  * Workspace bytes for jabba_kmeans with at most max_pieces pieces and a

@@ -21,6 +21,8 @@ JABBA_ECAPACITY = -4
 JABBA_ENONFINITE = -5
 JABBA_EOVERFLOW = -6
 JABBA_ENODEV = -7
+JABBA_ELIMIT = -8
+JABBA_ENCODE_NOALLOC_MAX_CAPACITY = 65536
 
 EXPORTS = [
     "jabba_abi_version", "jabba_status_str", "jabba_compress_workspace", "jabba_compress", "jabba_compress_plain",
@@ -29,7 +31,7 @@ EXPORTS = [
     "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
     "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans", "jabba_digitize_pca",
-    "jabba_axis_tolerances", "jabba_aggregate_points", "jabba_compress_znorm",
+    "jabba_axis_tolerances", "jabba_aggregate_points", "jabba_compress_znorm", "jabba_encode_noalloc",
 ]
 
 
@@ -96,6 +98,7 @@ def lib() -> C.CDLL:
             L.jabba_aggregate_points.argtypes = [P, P, P, I64, D, I32, P, I64, P, P, P, P, P, P, SZ, P]
             L.jabba_encode_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_encode.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
+            L.jabba_encode_noalloc.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P]
             L.jabba_reconstruct_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_reconstruct_size.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
             L.jabba_reconstruct.argtypes = [P, P, P, I64, P, C.POINTER(Dict), P, P, P, P, P, P, P]

@@ -16,7 +16,7 @@ import torch
 from . import _lib as L
 
 __all__ = [
-    "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "reconstruct",
+    "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "encode_noalloc", "reconstruct",
     "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
     "timing_enable", "timing_report", "digitize_stats", "digitize_quality", "kmeans", "axis_tolerances",
     "aggregate_points",
@@ -371,6 +371,16 @@ def encode(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_
     rc = L.lib().jabba_encode(_p(length), _p(inc), _p(n_pieces), int(max_pieces), C.byref(d), _p(symbols),
                               _p(workspace), workspace.numel(), _stream(stream))
     L.check(rc, "jabba_encode")
+    return symbols
+
+
+def encode_noalloc(length: torch.Tensor, inc: torch.Tensor, n_pieces: torch.Tensor, max_pieces: int,
+                   dictionary: Dictionary, symbols: torch.Tensor, stream=None) -> torch.Tensor:
+    """jabba_encode_noalloc: the same symbols with the library's own per-GPU scratch (no workspace)."""
+    d = dictionary.struct()
+    rc = L.lib().jabba_encode_noalloc(_p(length), _p(inc), _p(n_pieces), int(max_pieces), C.byref(d), _p(symbols),
+                                      _stream(stream))
+    L.check(rc, "jabba_encode_noalloc")
     return symbols
 
 

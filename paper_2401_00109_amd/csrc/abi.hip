@@ -163,6 +163,7 @@ extern "C" const char *jabba_status_str(int status) {
         case JABBA_ENONFINITE: return "non-finite input value";
         case JABBA_EOVERFLOW: return "count overflow";
         case JABBA_ENODEV: return "no gfx950 device";
+        case JABBA_ELIMIT: return "size above the fixed maximum of an allocation-free call";
         default: return "unknown status";
     }
 }

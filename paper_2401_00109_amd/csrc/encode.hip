@@ -16,6 +16,8 @@
 // product.
 #include "common.h"
 
+#include <mutex>
+
 namespace jabba {
 namespace {
 
@@ -268,28 +270,42 @@ EncWs carve_enc(void *ws, int64_t capacity) {
 }
 
 }  // namespace
-}  // namespace jabba
 
-using namespace jabba;
+// ----------------------------------------------------------- allocation-free
+// Scratch of jabba_encode_noalloc: the encode workspace of a dictionary of
+// JABBA_ENCODE_NOALLOC_MAX_CAPACITY centers, held in a file-scope device
+// array.  Every device the library runs on holds its own copy, at its own
+// address, until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in symbol); it passes the
+// device address that hipGetSymbolAddress returned for the current device.
+constexpr size_t kNoallocScratchBytes = 3u << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
-extern "C" int jabba_encode_workspace(int64_t capacity, size_t *bytes) {
-    if (!bytes || capacity < 1 || capacity > (1 << 30)) return JABBA_EINVAL;
-    *bytes = carve_enc(nullptr, capacity).bytes;
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch, looked up once per device with
+// that device current.  JABBA_EHIP when the runtime cannot resolve it.
+int scratch_address(void **out) {
+    int dev = -1;
+    JB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return JABBA_EHIP;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        JB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return JABBA_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return JABBA_OK;
 }
 
-extern "C" int jabba_encode(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
-                            const jabba_dict *dict, int32_t *symbols, void *workspace, size_t workspace_bytes,
-                            void *stream) {
-    if (!dict || !n_pieces || max_pieces < 0) return JABBA_EINVAL;
-    if (max_pieces == 0) return JABBA_OK;
-    if (!len || !inc || !symbols || !dict->params || !dict->k || dict->capacity < 1 || !dict->cx || !dict->cy)
-        return JABBA_EINVAL;
-    if (dict->capacity > (1 << 30)) return JABBA_EINVAL;
-    const EncWs w0 = carve_enc(nullptr, dict->capacity);
-    if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+int encode_launch(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                  const jabba_dict *dict, int32_t *symbols, void *workspace, hipStream_t st) {
     const EncWs w = carve_enc(workspace, dict->capacity);
-    hipStream_t st = (hipStream_t)stream;
     JB_LAUNCH(k_enc_sort, dim3(1), dim3(1024), 0, st, dict->k, dict->capacity, w.P, dict->cx, dict->cy, w.kx, w.ky,
               w.id, w.scy, w.sid, w.col_x, w.col_start, w.n_col);
     JB_LAUNCH_CHECK();
@@ -304,4 +320,45 @@ extern "C" int jabba_encode(const int32_t *len, const double *inc, const int64_t
                   dict->params, dict->k, dict->capacity, w.scy, w.sid, w.col_x, w.col_start, w.n_col, symbols);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
+}
+
+int encode_check(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                 const jabba_dict *dict, int32_t *symbols) {
+    if (!dict || !n_pieces || max_pieces < 0) return JABBA_EINVAL;
+    if (max_pieces == 0) return JABBA_OK;
+    if (!len || !inc || !symbols || !dict->params || !dict->k || dict->capacity < 1 || !dict->cx || !dict->cy)
+        return JABBA_EINVAL;
+    if (dict->capacity > (1 << 30)) return JABBA_EINVAL;
+    return JABBA_OK;
+}
+}  // namespace
+}  // namespace jabba
+
+using namespace jabba;
+
+extern "C" int jabba_encode_workspace(int64_t capacity, size_t *bytes) {
+    if (!bytes || capacity < 1 || capacity > (1 << 30)) return JABBA_EINVAL;
+    *bytes = carve_enc(nullptr, capacity).bytes;
+    return JABBA_OK;
+}
+
+extern "C" int jabba_encode(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
+                            const jabba_dict *dict, int32_t *symbols, void *workspace, size_t workspace_bytes,
+                            void *stream) {
+    const int rc = encode_check(len, inc, n_pieces, max_pieces, dict, symbols);
+    if (rc != JABBA_OK || max_pieces == 0) return rc;
+    if (!workspace || workspace_bytes < carve_enc(nullptr, dict->capacity).bytes) return JABBA_ENOMEM;
+    return encode_launch(len, inc, n_pieces, max_pieces, dict, symbols, workspace, (hipStream_t)stream);
+}
+
+extern "C" int jabba_encode_noalloc(const int32_t *len, const double *inc, const int64_t *n_pieces,
+                                    int64_t max_pieces, const jabba_dict *dict, int32_t *symbols, void *stream) {
+    const int rc = encode_check(len, inc, n_pieces, max_pieces, dict, symbols);
+    if (rc != JABBA_OK || max_pieces == 0) return rc;
+    if (dict->capacity > JABBA_ENCODE_NOALLOC_MAX_CAPACITY) return JABBA_ELIMIT;
+    if (carve_enc(nullptr, dict->capacity).bytes > kNoallocScratchBytes) return JABBA_ELIMIT;
+    void *ws = nullptr;
+    const int ra = scratch_address(&ws);
+    if (ra != JABBA_OK) return ra;
+    return encode_launch(len, inc, n_pieces, max_pieces, dict, symbols, ws, (hipStream_t)stream);
 }

@@ -74,3 +74,20 @@ def test_every_export_has_a_ctypes_signature():
     L = _lib.lib()
     for name in _lib.EXPORTS:
         assert getattr(L, name).argtypes is not None, f"{name} has no ctypes signature"
+
+
+def test_noalloc_encode_limit_is_host_checked():
+    # the allocation-free encode's scratch holds the workspace of its maximum
+    # capacity, and larger dictionaries are refused before any HIP call
+    from paper_2401_00109_amd import _lib
+    L = _lib.lib()
+    n = C.c_size_t()
+    assert L.jabba_encode_workspace(_lib.JABBA_ENCODE_NOALLOC_MAX_CAPACITY, C.byref(n)) == 0
+    assert n.value <= 3 << 20
+    d = _lib.Dict()
+    d.capacity = _lib.JABBA_ENCODE_NOALLOC_MAX_CAPACITY + 1
+    fake = C.c_void_p(256)
+    d.params = d.k = d.cx = d.cy = fake
+    rc = L.jabba_encode_noalloc(fake, fake, fake, 10, C.byref(d), fake, None)
+    assert rc == _lib.JABBA_ELIMIT
+    assert _lib.status_str(rc).startswith("size above")
