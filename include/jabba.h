@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define JABBA_ABI_VERSION 2
+#define JABBA_ABI_VERSION 3
 
 enum jabba_status {
     JABBA_OK = 0,
@@ -514,14 +514,30 @@ typedef struct jabba_plan_desc {
     size_t compress_ws_bytes;
     void *digitize_ws;
     size_t digitize_ws_bytes;
-    jabba_tuning tuning;
+    /* launch shapes; NULL = autotuned by jabba_plan_create */
+    const jabba_tuning *tuning;
 } jabba_plan_desc;
 
 /*
  * Captures the path for the buffers and sizes in *desc (they are bound to the
  * plan) on an internal stream and instantiates the graph.  Synchronous.
+ *
+ * With desc->tuning NULL the launch shapes are chosen first, on the plan's
+ * own buffers and inputs: the compression is timed over lanes per domain
+ * {1, 2, 4} x wavefronts per workgroup {1, 2, 4} x workgroups per compute
+ * unit {2, 4, 8}, then the digitization over Stage I wavefronts {1, 2, 4}
+ * (best of two runs each).  Every variant's output is compared on the device
+ * with the default launch's (pieces, offsets and count, using the digitize
+ * workspace for the copy; symbols, using the compress workspace) whenever
+ * that workspace can hold the copy, and a variant that differs is never
+ * chosen.  The inputs are read and the outputs written during the search,
+ * which costs a few dozen runs of the path.  jabba_plan_tuning reports the
+ * choice.
  */
 int jabba_plan_create(const jabba_plan_desc *desc, jabba_plan **plan);
+
+/* The launch shapes the plan was captured with (the caller's or the autotuned ones). */
+int jabba_plan_tuning(const jabba_plan *plan, jabba_tuning *tuning);
 
 /* Replays the captured graph on `stream` (asynchronous). */
 int jabba_plan_run(jabba_plan *plan, void *stream);

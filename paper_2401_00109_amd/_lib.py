@@ -28,7 +28,7 @@ EXPORTS = [
     "jabba_abi_version", "jabba_status_str", "jabba_compress_workspace", "jabba_compress", "jabba_compress_plain",
     "jabba_digitize_workspace", "jabba_digitize", "jabba_encode_workspace", "jabba_encode", "jabba_reconstruct_workspace",
     "jabba_reconstruct_size", "jabba_reconstruct", "jabba_reconstruct_pieces", "jabba_workspace_status",
-    "jabba_plan_create", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
+    "jabba_plan_create", "jabba_plan_tuning", "jabba_plan_run", "jabba_plan_destroy", "jabba_fp64_selftest",
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
     "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans", "jabba_digitize_pca",
     "jabba_axis_tolerances", "jabba_aggregate_points", "jabba_compress_znorm", "jabba_encode_noalloc",
@@ -54,7 +54,7 @@ class PlanDesc(C.Structure):
         ("symbols", C.c_void_p), ("dict", Dict),
         ("compress_ws", C.c_void_p), ("compress_ws_bytes", C.c_size_t),
         ("digitize_ws", C.c_void_p), ("digitize_ws_bytes", C.c_size_t),
-        ("tuning", Tuning),
+        ("tuning", C.POINTER(Tuning)),
     ]
 
 
@@ -105,6 +105,7 @@ def lib() -> C.CDLL:
             L.jabba_reconstruct_pieces.argtypes = [P, P, P, P, I64, P, P, P, P, SZ, P]
             L.jabba_workspace_status.argtypes = [P, P, C.POINTER(C.c_int32)]
             L.jabba_plan_create.argtypes = [C.POINTER(PlanDesc), C.POINTER(P)]
+            L.jabba_plan_tuning.argtypes = [P, C.POINTER(Tuning)]
             L.jabba_plan_run.argtypes = [P, P]
             L.jabba_plan_destroy.argtypes = [P]
             L.jabba_fp64_selftest.argtypes = [P, P, P, P, I64, P]

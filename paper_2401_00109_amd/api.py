@@ -428,25 +428,35 @@ def reconstruct_pieces(length: torch.Tensor, inc: torch.Tensor, piece_off: torch
 
 
 class Plan:
-    """Compress + digitize captured once into a HIP graph; run() replays it."""
+    """Compress + digitize captured once into a HIP graph; run() replays it.
+
+    tuning None lets jabba_plan_create choose the launch shapes (autotune);
+    tuning() reports the shapes the graph was captured with."""
 
     def __init__(self, values: torch.Tensor, series_off: torch.Tensor, D: int, tol: float, alpha: float,
                  scl: float = 1.0, B: int = 4096, max_len: int = 0, max_pieces: int | None = None,
-                 capacity: int | None = None, tuning: dict | None = None):
+                 capacity: int | None = None, tuning: dict | None = None, buffers: "Symbolizer | None" = None):
         dev = values.device
         self.n_series = series_off.numel() - 1
         self.total = values.numel()
-        self.max_pieces = int(max_pieces) if max_pieces is not None else max(self.total, 1)
-        mp = self.max_pieces
         self.values, self.series_off = values, series_off
-        self.pieces = Pieces(torch.empty(mp, dtype=torch.int32, device=dev),
-                             torch.empty(mp, dtype=torch.float64, device=dev),
-                             torch.empty(self.n_series + 1, dtype=torch.int64, device=dev),
-                             torch.empty(1, dtype=torch.int64, device=dev), mp)
-        self.symbols = torch.empty(mp, dtype=torch.int32, device=dev)
-        self.dictionary = Dictionary(capacity if capacity is not None else mp, dev)
-        self.cws = _ws(compress_workspace_bytes(self.n_series, self.total, D), dev)
-        self.dws = _ws(digitize_workspace_bytes(mp, B), dev)
+        if buffers is not None:
+            # share an eager Symbolizer's buffers (sized for its piece count)
+            self.max_pieces = buffers.max_pieces
+            self.pieces, self.symbols, self.dictionary = buffers.pieces, buffers.symbols, buffers.dictionary
+            self.cws, self.dws = buffers.cws, buffers.dws
+        else:
+            self.max_pieces = int(max_pieces) if max_pieces is not None else max(self.total, 1)
+            mp = self.max_pieces
+            self.pieces = Pieces(torch.empty(mp, dtype=torch.int32, device=dev),
+                                 torch.empty(mp, dtype=torch.float64, device=dev),
+                                 torch.empty(self.n_series + 1, dtype=torch.int64, device=dev),
+                                 torch.empty(1, dtype=torch.int64, device=dev), mp)
+            self.symbols = torch.empty(mp, dtype=torch.int32, device=dev)
+            self.dictionary = Dictionary(capacity if capacity is not None else mp, dev)
+            self.cws = _ws(compress_workspace_bytes(self.n_series, self.total, D), dev)
+            self.dws = _ws(digitize_workspace_bytes(mp, B), dev)
+        mp = self.max_pieces
         desc = L.PlanDesc()
         desc.values, desc.series_off = values.data_ptr(), series_off.data_ptr()
         desc.n_series, desc.total_points, desc.D, desc.tol = self.n_series, self.total, int(D), float(tol)
@@ -459,11 +469,25 @@ class Plan:
         desc.digitize_ws, desc.digitize_ws_bytes = self.dws.data_ptr(), self.dws.numel()
         t = tuning_struct(tuning)
         if t is not None:
-            desc.tuning = t
+            desc.tuning = C.pointer(t)
         torch.cuda.synchronize(dev)
         h = C.c_void_p()
         L.check(L.lib().jabba_plan_create(C.byref(desc), C.byref(h)), "jabba_plan_create")
         self._h = h
+
+    @classmethod
+    def from_symbolizer(cls, sz: "Symbolizer", values: torch.Tensor, series_off: torch.Tensor,
+                        tuning: dict | None = None) -> "Plan":
+        """A plan over an eager Symbolizer's own buffers (no second set); the
+        graph and the Symbolizer then write the same outputs."""
+        return cls(values, series_off, sz.D, sz.tol, sz.alpha, sz.scl, sz.B, sz.max_len, tuning=tuning, buffers=sz)
+
+    def tuning(self) -> dict:
+        t = L.Tuning()
+        L.check(L.lib().jabba_plan_tuning(self._h, C.byref(t)), "jabba_plan_tuning")
+        return {"lanes_per_domain": t.lanes_per_domain, "waves_per_block": t.waves_per_block,
+                "blocks_per_cu": t.blocks_per_cu, "stage1_waves": t.stage1_waves,
+                "segment_intervals": t.segment_intervals}
 
     def run(self, stream=None) -> None:
         L.check(L.lib().jabba_plan_run(self._h, _stream(stream)), "jabba_plan_run")

@@ -57,6 +57,7 @@ __all__ = [
     "WORKLOADS",
     "Request",
     "request_stream",
+    "request_pool",
 ]
 
 
@@ -210,20 +211,35 @@ class Request:
     series_off: np.ndarray
 
 
+def _request_body(seed: int, r: int, max_series: int, min_len: int, max_len: int):
+    rng = series_rng(seed, 5, r + 1)
+    ns = int(rng.integers(1, max_series + 1))
+    ser = []
+    for _ in range(ns):
+        n = int(math.floor(math.exp(rng.uniform(math.log(min_len), math.log(max_len)))))
+        ser.append(znorm(random_walk(rng, n)))
+    return pack(ser)
+
+
 def request_stream(seed: int, n_requests: int, rate_hz: float, max_series: int = 256,
-                   min_len: int = 500, max_len: int = 50_000, first_id: int = 0) -> list[Request]:
-    """Poisson arrivals (exponential gaps at ``rate_hz``); 1..max_series random walks each."""
+                   min_len: int = 500, max_len: int = 50_000, first_id: int = 0,
+                   pool: list[tuple[np.ndarray, np.ndarray]] | None = None) -> list[Request]:
+    """Poisson arrivals (exponential gaps at ``rate_hz``); 1..max_series random walks each.
+
+    With ``pool`` (bodies from ``request_pool``) request r carries body
+    r mod len(pool) instead of freshly drawn series, so long request streams
+    need no more host memory than the pool."""
     out = []
     t = 0.0
     arr = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 5, 0x5EED])))
     for r in range(first_id, first_id + n_requests):
         t += float(arr.exponential(1.0 / rate_hz)) if rate_hz > 0 else 0.0
-        rng = series_rng(seed, 5, r + 1)
-        ns = int(rng.integers(1, max_series + 1))
-        ser = []
-        for _ in range(ns):
-            n = int(math.floor(math.exp(rng.uniform(math.log(min_len), math.log(max_len)))))
-            ser.append(znorm(random_walk(rng, n)))
-        v, off = pack(ser)
+        v, off = pool[r % len(pool)] if pool else _request_body(seed, r, max_series, min_len, max_len)
         out.append(Request(r, t, v, off))
     return out
+
+
+def request_pool(seed: int, n_bodies: int, max_series: int = 256, min_len: int = 500,
+                 max_len: int = 50_000) -> list[tuple[np.ndarray, np.ndarray]]:
+    """n_bodies request bodies (values, series_off) drawn as request_stream draws them."""
+    return [_request_body(seed, r, max_series, min_len, max_len) for r in range(n_bodies)]

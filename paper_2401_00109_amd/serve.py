@@ -73,6 +73,7 @@ class Server:
         # arena: memory the in-flight requests may hold; a request needs ~ its points x 24 B
         self.arena = arena_bytes if arena_bytes is not None else slots * max_points * 24
         self.in_use = 0
+        self.peak_in_flight = 0  # most requests on the device at once during the last run()
 
     @staticmethod
     def need(points: int) -> int:
@@ -113,6 +114,7 @@ class Server:
         """Serve `requests` (inputs.Request, arrival offsets in seconds from now)."""
         pending = sorted(requests, key=lambda r: r.arrival_s)
         waiting, out = [], []
+        self.peak_in_flight = 0
         t0 = time.perf_counter()
         i = 0
         while i < len(pending) or waiting or any(s.req is not None for s in self.slots):
@@ -144,6 +146,7 @@ class Server:
                 self.in_use += self.need(r.values.size)
                 s.req = (r, time.perf_counter() - t0)
                 self._launch(s, r)
+                self.peak_in_flight = max(self.peak_in_flight, sum(1 for q in self.slots if q.req is not None))
             if i < len(pending) and not waiting and all(s.req is None for s in self.slots):
                 # idle until the next arrival
                 dt = pending[i].arrival_s - (time.perf_counter() - t0)

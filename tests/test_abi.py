@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     L = _lib.lib()
     for name in declared_functions():
         assert hasattr(L, name), f"{name} declared in jabba.h but not exported"
-    assert L.jabba_abi_version() == 2
+    assert L.jabba_abi_version() == 3
     assert set(_lib.EXPORTS) == set(declared_functions())
 
 

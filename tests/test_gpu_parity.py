@@ -385,6 +385,42 @@ def test_plan_graph_replays_match_eager():
     plan.close()
 
 
+def test_autotuned_plan_on_symbolizer_buffers():
+    # no tuning: jabba_plan_create picks the launch shapes (output-checked on the
+    # device); the plan shares the eager Symbolizer's buffers, sized for the
+    # live piece count, and its replays equal the oracle
+    import paper_2401_00109_amd as J
+    T = torch()
+    w = _workload(3)
+    v, so = to_dev(w.values), to_dev(w.series_off)
+    ol, oi, opo = O.compress(w.values, w.series_off, w.D, w.tol)
+    od = O.digitize(ol, oi, w.alpha, w.scl, w.B)
+    sz = J.Symbolizer(w.n_series, w.n_points, w.D, w.tol, w.alpha, w.scl, w.B, max_pieces=ol.size)
+    say(f"autotuned plan: {w.n_series} series, {ol.size} pieces")
+    plan = J.Plan.from_symbolizer(sz, v, so)
+    t = plan.tuning()
+    say(f"  chosen {t}")
+    assert t["lanes_per_domain"] in (1, 2, 4) and t["waves_per_block"] in (1, 2, 4)
+    assert t["blocks_per_cu"] in (2, 4, 8) and t["stage1_waves"] in (1, 2, 4)
+    for rep in range(3):
+        sz.symbols.fill_(-1)
+        sz.pieces.len.fill_(-1)
+        T.cuda.synchronize()
+        plan.run()
+        T.cuda.synchronize()
+        ln, inc, po = sz.pieces.host()
+        np.testing.assert_array_equal(ln, ol)
+        np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+        np.testing.assert_array_equal(po, opo)
+        np.testing.assert_array_equal(sz.symbols[: ol.size].cpu().numpy(), od.symbols)
+        assert sz.dictionary.size() == od.k
+        sz.run(v, so)  # eager work on the same buffers between replays
+        T.cuda.synchronize()
+        np.testing.assert_array_equal(sz.symbols[: ol.size].cpu().numpy(), od.symbols)
+    assert plan.status() == (0, 0)
+    plan.close()
+
+
 # ------------------------------------------------------------------ full size
 @pytest.fixture(scope="module")
 def full_scale():
