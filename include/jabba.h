@@ -23,6 +23,9 @@
  *    stay in device memory; no call synchronises the host, except
  *    jabba_workspace_status and the plan/tuning helpers that say so.
  *  - Host-detected errors are returned immediately and nothing is enqueued.
+ *    Every call that enqueues work first checks, after its arguments, that
+ *    the current device is a gfx950 (JABBA_ENODEV otherwise, also when no
+ *    device is visible).
  *    Device-detected errors (a non-finite input value, a dictionary that is
  *    too small) are OR-ed into a status word held in the call's workspace;
  *    read it with jabba_workspace_status after the stream has run.
@@ -430,6 +433,15 @@ int jabba_reconstruct_size(const int32_t *symbols, const int64_t *piece_off, con
 int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off, int64_t n_series,
                       const double *t0, const jabba_dict *dict, const int64_t *out_off, double *out, int64_t *lhat,
                       const double *values, double *sse, int64_t *cnt, void *stream);
+
+/*
+ * Mean squared error of a reconstruction (Sec. 3.3): mse[0] (device) =
+ * sum(sse) / sum(cnt) over the n_series per-series outputs of
+ * jabba_reconstruct.  The squared errors are added by a balanced pairwise
+ * tree over the series (leaves in series order, zero-padded to a power of
+ * two), the counts exactly; 0 when no point was compared.
+ */
+int jabba_reconstruct_mse(const double *sse, const int64_t *cnt, int64_t n_series, double *mse, void *stream);
 
 /*
  * Inverse compression straight from (len, inc) (Sec. 3.1: the polygonal

@@ -211,8 +211,11 @@ int jo_znorm(const double *values, const int64_t *series_off, int64_t n_series, 
  * Exact sum rounded once to binary64: the running sum is kept as a list of
  * non-overlapping partials updated with error-free two-sum steps (Shewchuk,
  * "Adaptive precision floating-point arithmetic", 1997), then the partials
- * are added from the largest down with a final half-way correction.  Used for
- * the dictionary means, whose reference value is the mean of the members.
+ * are added from the largest down with a final half-way correction.  The
+ * partials update and the half-way correction follow CPython's math.fsum,
+ * which implements the same method and which the tests pin this sum against.
+ * Used for the dictionary means, whose reference value is the mean of the
+ * members.
  */
 typedef struct {
     double *p;

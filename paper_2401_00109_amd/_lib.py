@@ -32,6 +32,7 @@ EXPORTS = [
     "jabba_timing_enable", "jabba_timing_get", "jabba_timing_names", "jabba_digitize_stats",
     "jabba_digitize_quality", "jabba_kmeans_workspace", "jabba_kmeans", "jabba_digitize_pca",
     "jabba_axis_tolerances", "jabba_aggregate_points", "jabba_compress_znorm", "jabba_encode_noalloc",
+    "jabba_reconstruct_mse",
 ]
 
 
@@ -102,6 +103,7 @@ def lib() -> C.CDLL:
             L.jabba_reconstruct_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_reconstruct_size.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
             L.jabba_reconstruct.argtypes = [P, P, P, I64, P, C.POINTER(Dict), P, P, P, P, P, P, P]
+            L.jabba_reconstruct_mse.argtypes = [P, P, I64, P, P]
             L.jabba_reconstruct_pieces.argtypes = [P, P, P, P, I64, P, P, P, P, SZ, P]
             L.jabba_workspace_status.argtypes = [P, P, C.POINTER(C.c_int32)]
             L.jabba_plan_create.argtypes = [C.POINTER(PlanDesc), C.POINTER(P)]

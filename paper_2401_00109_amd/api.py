@@ -17,7 +17,7 @@ from . import _lib as L
 
 __all__ = [
     "Pieces", "Dictionary", "compress", "compress_plain", "digitize", "encode", "encode_noalloc", "reconstruct",
-    "reconstruct_pieces", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
+    "reconstruct_pieces", "reconstruction_mse", "workspace_status", "Plan", "tuning_struct", "Symbolizer", "Reconstructor",
     "timing_enable", "timing_report", "digitize_stats", "digitize_quality", "kmeans", "axis_tolerances",
     "aggregate_points",
 ]
@@ -409,6 +409,14 @@ def reconstruct(symbols: torch.Tensor, piece_off: torch.Tensor, series_off: torc
     return {"out": out[:total], "out_off": out_off, "lhat": lhat, "sse": sse, "cnt": cnt, "status": status}
 
 
+def reconstruction_mse(sse: torch.Tensor, cnt: torch.Tensor, n_series: int, stream=None) -> float:
+    """Mean squared error from jabba_reconstruct's per-series outputs (jabba_reconstruct_mse); synchronises."""
+    out = torch.empty(1, dtype=torch.float64, device=sse.device)
+    L.check(L.lib().jabba_reconstruct_mse(_p(sse), _p(cnt), int(n_series), _p(out), _stream(stream)),
+            "jabba_reconstruct_mse")
+    return float(out.item())
+
+
 def reconstruct_pieces(length: torch.Tensor, inc: torch.Tensor, piece_off: torch.Tensor, series_off: torch.Tensor,
                        t0: torch.Tensor, total_out: int | None = None, stream=None):
     """Polyline straight from the pieces.  Returns (out, out_off)."""
@@ -598,9 +606,9 @@ class Reconstructor:
                                           _p(self.cnt) if v is not None else None, _stream(stream)),
                 "jabba_reconstruct")
 
-    def mse(self) -> float:
-        c = int(self.cnt[: self.ns].sum().item())
-        return float(self.sse[: self.ns].sum().item()) / max(c, 1)
+    def mse(self, stream=None) -> float:
+        """Sec. 3.3 mean squared error of the last run (jabba_reconstruct_mse); synchronises."""
+        return reconstruction_mse(self.sse, self.cnt, self.ns, stream)
 
 
 def timing_enable(on: bool = True) -> None:

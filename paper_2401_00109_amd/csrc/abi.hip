@@ -90,6 +90,20 @@ int device_cu_count() {
     return cache[dev];
 }
 
+int device_check() {
+    static int cache[64] = {0};  // 0 unknown, 1 gfx950, 2 another device
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return JABBA_ENODEV;
+    if (!cache[dev]) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return JABBA_ENODEV;
+        const char *a = prop.gcnArchName;
+        cache[dev] = (a[0] == 'g' && a[1] == 'f' && a[2] == 'x' && a[3] == '9' && a[4] == '5' && a[5] == '0' &&
+                      (a[6] == 0 || a[6] == ':')) ? 1 : 2;
+    }
+    return cache[dev] == 1 ? JABBA_OK : JABBA_ENODEV;
+}
+
 namespace {
 __global__ void k_fp64_selftest(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ q,
                                 double *__restrict__ r, int64_t n) {
@@ -106,6 +120,7 @@ extern "C" int jabba_fp64_selftest(const double *a, const double *b, double *quo
                                    void *stream) {
     if (n < 0 || (n > 0 && (!a || !b || !quot || !root))) return JABBA_EINVAL;
     if (n == 0) return JABBA_OK;
+    JB_DEVICE_CHECK();
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     JB_LAUNCH(jabba::k_fp64_selftest, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a, b, quot,

@@ -55,6 +55,15 @@ struct Carve {
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
+// JABBA_OK when the current device is a gfx950 (cached per device), else
+// JABBA_ENODEV (also when no device is visible).
+int device_check();
+#define JB_DEVICE_CHECK()                           \
+    do {                                            \
+        const int dc_ = ::jabba::device_check();    \
+        if (dc_ != JABBA_OK) return dc_;            \
+    } while (0)
+
 // Opt-in per-kernel event timing (jabba_timing_*): a scope that records an
 // event on `st` when created and another when destroyed, if timing is on.
 // Times the launches enqueued during its lifetime on one stream as `launches`

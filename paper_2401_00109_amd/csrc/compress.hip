@@ -834,6 +834,7 @@ extern "C" int jabba_compress(const double *values, const int64_t *series_off, i
     if (rc) return rc;
     CompressWs w0 = carve_compress(nullptr, n_series, total_points, D);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     CompressWs w = carve_compress(workspace, n_series, total_points, D);
     hipStream_t st = (hipStream_t)stream;
     int W = kDefaultW, wpb = kDefaultWavesPerBlock, bpc = kDefaultBlocksPerCu;
@@ -874,6 +875,7 @@ extern "C" int jabba_compress_znorm(const double *values, const int64_t *series_
     if (n_series > 0 && (!mean || !std_dev)) return JABBA_EINVAL;
     CompressWs w0 = carve_compress(nullptr, n_series, total_points, D);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     CompressWs w = carve_compress(workspace, n_series, total_points, D);
     hipStream_t st = (hipStream_t)stream;
     int W = kDefaultW, wpb = kDefaultWavesPerBlock, bpc = kDefaultBlocksPerCu;
@@ -922,6 +924,7 @@ extern "C" int jabba_compress_plain(const double *values, const int64_t *series_
     if (rc) return rc;
     CompressWs w0 = carve_compress(nullptr, n_series, total_points, D);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     CompressWs w = carve_compress(workspace, n_series, total_points, D);
     hipStream_t st = (hipStream_t)stream;
     rc = domain_table(w, series_off, n_series, total_points, D, D, false, st);

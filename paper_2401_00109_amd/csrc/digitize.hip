@@ -1315,6 +1315,7 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
         return JABBA_EINVAL;
     const DigWs w0 = carve_digitize(nullptr, max_pieces, B);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     const DigWs w = carve_digitize(workspace, max_pieces, B);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = max_pieces > 0 ? max_pieces : 1;
@@ -1457,6 +1458,7 @@ extern "C" int jabba_aggregate_points(const double *x, const double *y, const in
     if (capacity > 0 && (!cx || !cy || !count)) return JABBA_EINVAL;
     const DigWs w0 = carve_digitize(nullptr, max_points, B);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     const DigWs w = carve_digitize(workspace, max_points, B);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = max_points > 0 ? max_points : 1;
@@ -1612,6 +1614,7 @@ extern "C" int jabba_digitize_quality(const int32_t *len, const double *inc, con
     if (dict->capacity < 1 || !dict->k || !dict->cx || !dict->cy || !dict->count) return JABBA_EINVAL;
     const DigWs w0 = carve_digitize(nullptr, max_pieces, B);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     const DigWs w = carve_digitize(workspace, max_pieces, B);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = max_pieces > 0 ? max_pieces : 1;

@@ -305,6 +305,7 @@ int scratch_address(void **out) {
 
 int encode_launch(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces,
                   const jabba_dict *dict, int32_t *symbols, void *workspace, hipStream_t st) {
+    JB_DEVICE_CHECK();
     const EncWs w = carve_enc(workspace, dict->capacity);
     JB_LAUNCH(k_enc_sort, dim3(1), dim3(1024), 0, st, dict->k, dict->capacity, w.P, dict->cx, dict->cy, w.kx, w.ky,
               w.id, w.scy, w.sid, w.col_x, w.col_start, w.n_col);
@@ -357,6 +358,7 @@ extern "C" int jabba_encode_noalloc(const int32_t *len, const double *inc, const
     if (rc != JABBA_OK || max_pieces == 0) return rc;
     if (dict->capacity > JABBA_ENCODE_NOALLOC_MAX_CAPACITY) return JABBA_ELIMIT;
     if (carve_enc(nullptr, dict->capacity).bytes > kNoallocScratchBytes) return JABBA_ELIMIT;
+    JB_DEVICE_CHECK();
     void *ws = nullptr;
     const int ra = scratch_address(&ws);
     if (ra != JABBA_OK) return ra;

@@ -162,6 +162,7 @@ extern "C" int jabba_kmeans(const int32_t *len, const double *inc, const int64_t
         return JABBA_EINVAL;
     const KmWs w0 = carve_km(nullptr, max_pieces, dict->capacity);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     const KmWs w = carve_km(workspace, max_pieces, dict->capacity);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = max_pieces > 0 ? max_pieces : 1;

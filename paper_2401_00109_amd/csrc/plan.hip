@@ -201,6 +201,7 @@ extern "C" int jabba_plan_create(const jabba_plan_desc *d, jabba_plan **out) {
     if (!out) return JABBA_EINVAL;
     *out = nullptr;
     if (!d) return JABBA_EINVAL;
+    JB_DEVICE_CHECK();
     hipStream_t st;
     JB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     jabba_tuning chosen{};

@@ -424,6 +424,7 @@ int sizes(const Src &src, const int64_t *piece_off, const int64_t *series_off, i
     if (n_series < 0 || !piece_off || !series_off || !out_off) return JABBA_EINVAL;
     const ReconWs w0 = carve_recon(nullptr, n_series);
     if (!workspace || workspace_bytes < w0.bytes) return JABBA_ENOMEM;
+    JB_DEVICE_CHECK();
     const ReconWs w = carve_recon(workspace, n_series);
     JB_LAUNCH(k_recon_prep, dim3(1), dim3(64), 0, st, w.status);
     JB_LAUNCH_CHECK();
@@ -435,10 +436,57 @@ int sizes(const Src &src, const int64_t *piece_off, const int64_t *series_off, i
     return scan_i64_to_i64(w.cnt, out_off, nullptr, n_series, w.scan_ws, st);
 }
 
+// Mean squared error over all series (Sec. 3.3): the per-series squared
+// errors summed by a balanced pairwise tree over the series (leaves in series
+// order, zero-padded to a power of two, adjacent leaves paired first), the
+// point counts summed exactly, then one division.  One workgroup: each
+// thread sums a power-of-two run of leaves (a binary counter of partial sums
+// merges equal-size neighbours, which is the same tree), then the threads'
+// sums are paired level by level.
+constexpr int kMseThreads = 1024;
+__global__ __launch_bounds__(kMseThreads) void k_mse(const double *__restrict__ sse, const int64_t *__restrict__ cnt,
+                                                     int64_t n_series, double *__restrict__ mse) {
+    __shared__ double s_v[kMseThreads];
+    __shared__ unsigned long long s_c[kMseThreads];
+    int64_t per = 1;
+    while (per * kMseThreads < n_series) per <<= 1;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    double part[64];
+    int depth = 0;
+    unsigned long long c = 0;
+    for (int64_t i = 0; i < per; ++i) {
+        const int64_t j = lo + i;
+        double x = j < n_series ? sse[j] : 0.0;
+        if (j < n_series) c += (unsigned long long)cnt[j];
+        for (int64_t k = i + 1; (k & 1) == 0; k >>= 1) x = part[--depth] + x;
+        part[depth++] = x;
+    }
+    s_v[threadIdx.x] = part[0];
+    s_c[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 1; h < kMseThreads; h <<= 1) {
+        if ((threadIdx.x & (2 * h - 1)) == 0) {
+            s_v[threadIdx.x] = s_v[threadIdx.x] + s_v[threadIdx.x + h];
+            s_c[threadIdx.x] += s_c[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mse[0] = s_c[0] ? s_v[0] / (double)s_c[0] : 0.0;
+}
+
 }  // namespace
 }  // namespace jabba
 
 using namespace jabba;
+
+extern "C" int jabba_reconstruct_mse(const double *sse, const int64_t *cnt, int64_t n_series, double *mse,
+                                     void *stream) {
+    if (n_series < 0 || !mse || (n_series > 0 && (!sse || !cnt))) return JABBA_EINVAL;
+    JB_DEVICE_CHECK();
+    JB_LAUNCH(k_mse, dim3(1), dim3(kMseThreads), 0, (hipStream_t)stream, sse, cnt, n_series, mse);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
 
 extern "C" int jabba_reconstruct_workspace(int64_t n_series, size_t *bytes) {
     if (!bytes || n_series < 0) return JABBA_EINVAL;
@@ -465,6 +513,7 @@ extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_of
     hipStream_t st = (hipStream_t)stream;
     Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
     if (values && (!sse || !cnt)) return JABBA_EINVAL;
+    JB_DEVICE_CHECK();
     JB_LAUNCH_NAMED("k_recon", k_recon<true>, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off,
                     out_off, n_series, t0, out, lhat, series_off, values, sse, cnt);
     JB_LAUNCH_CHECK();

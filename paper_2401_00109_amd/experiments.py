@@ -70,9 +70,7 @@ def _mse(sym, dictionary, dom, dev):
     values, series_off, piece_off, t0 = dom
     r = api.reconstruct(sym, torch.from_numpy(piece_off).to(dev), torch.from_numpy(series_off).to(dev),
                         torch.from_numpy(t0).to(dev), dictionary, values=torch.from_numpy(values).to(dev))
-    sse = float(r["sse"].sum().item())
-    cnt = int(r["cnt"].sum().item())
-    return sse / max(cnt, 1)
+    return api.reconstruction_mse(r["sse"], r["cnt"], series_off.size - 1)
 
 
 def _sse(ln, ic, sym, h):
@@ -83,7 +81,9 @@ def _sse(ln, ic, sym, h):
 
 
 def noise_partitions(partitions, n: int = 100_000, tol: float = 0.01, alpha: float = 0.05, seed: int = 0,
-                     kmeans_iter: int = 100, kmeans_init: str = "aggregation", device=None) -> list[dict]:
+                     kmeans_iter: int = 100, kmeans_init: str = "aggregation", device=None,
+                     keep_symbols: bool = False) -> list[dict]:
+    """One row per partition count M; keep_symbols adds both digitizations' symbols (host arrays)."""
     if kmeans_init not in ("aggregation", "spread"):
         raise ValueError(f"kmeans_init must be 'aggregation' or 'spread', not {kmeans_init!r}")
     dev = torch.device("cuda", 0) if device is None else torch.device(device)
@@ -124,6 +124,9 @@ def noise_partitions(partitions, n: int = 100_000, tol: float = 0.01, alpha: flo
         rows.append({"M": M, "D": D, "pieces": N, "boundary_pieces": None if base_pieces is None else N - base_pieces,
                      "symbols": k, "mse_aggregation": mse_agg, "mse_kmeans": mse_km, "sse_aggregation": sse_agg,
                      "sse_kmeans": sse_km, "kmeans_iterations": int(iters.item())})
+        if keep_symbols:
+            rows[-1]["symbols_aggregation"] = sym[:N].cpu().numpy()
+            rows[-1]["symbols_kmeans"] = symk[:N].cpu().numpy()
     return rows
 
 
@@ -163,7 +166,7 @@ def digitizer_sweep(settings, workload_id: int = 2, scale: float = 1.0, seed: in
         row.update({"workload": workload_id, "pieces": N, "alpha_used": alpha, "scl_used": scl, "symbols": d.size(),
                     "starts": stats["G"], "sse": float(tot[0]), "max_var_len": float(tot[1]),
                     "max_var_inc": float(tot[2]),
-                    "mse": float(r["sse"].sum().item()) / max(int(r["cnt"].sum().item()), 1)})
+                    "mse": api.reconstruction_mse(r["sse"], r["cnt"], so.numel() - 1)})
         if key == "pca":
             row["axis"] = d.axis.cpu().numpy().tolist()
         rows.append(row)

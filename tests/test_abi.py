@@ -91,3 +91,17 @@ def test_noalloc_encode_limit_is_host_checked():
     rc = L.jabba_encode_noalloc(fake, fake, fake, 10, C.byref(d), fake, None)
     assert rc == _lib.JABBA_ELIMIT
     assert _lib.status_str(rc).startswith("size above")
+
+
+def test_device_check_refuses_without_a_gfx950():
+    # valid arguments on a machine with no visible GPU: nothing can be
+    # enqueued, and the call says why instead of failing inside HIP
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2401_00109_amd import _lib
+    L = _lib.lib()
+    fake = C.c_void_p(256)
+    rc = L.jabba_fp64_selftest(fake, fake, fake, fake, 10, None)
+    assert rc == _lib.JABBA_ENODEV
+    assert _lib.status_str(rc) == "no gfx950 device"

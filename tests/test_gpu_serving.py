@@ -37,6 +37,34 @@ def test_mix_equals_alone_and_oracle(arena_points):
     say(f"serving 12 requests, 3 slots, arena={arena}")
     mixed = {r.rid: r for r in srv.run(reqs, realtime=True)}
     assert len(mixed) == 12
+    say(f"  at most {srv.peak_in_flight} requests in flight")
+    if arena is None:
+        assert srv.peak_in_flight > 1  # the requests did overlap on the device
+    for r in reqs:
+        alone = srv.run([r], realtime=False)[0]
+        m = mixed[r.rid]
+        np.testing.assert_array_equal(alone.symbols, m.symbols)
+        np.testing.assert_array_equal(alone.piece_off, m.piece_off)
+        ln, inc, po = O.compress(r.values, r.series_off, 2000, 0.05)
+        exp = O.encode(ln, inc, od.sigma_len, od.sigma_inc, od.scl, od.cx, od.cy)
+        np.testing.assert_array_equal(m.symbols, exp)
+        np.testing.assert_array_equal(m.piece_off, po)
+
+
+def test_full_size_requests_mix_equals_alone_and_oracle():
+    # requests of the serving workload's full shape: 1-256 random walks of
+    # 500-50,000 points each, four slots, arrivals faster than service
+    from paper_2401_00109_amd.serve import Server
+    od, d = _oracle_dictionary()
+    reqs = request_stream(11, 8, rate_hz=5000.0)
+    pts = [r.values.size for r in reqs]
+    say(f"serving 8 full-size requests ({min(pts)}-{max(pts)} points, "
+        f"{max(r.series_off.size - 1 for r in reqs)} series at most), 4 slots")
+    srv = Server(d, D=2000, tol=0.05, slots=4, device=DEV)
+    mixed = {r.rid: r for r in srv.run(reqs, realtime=True)}
+    assert len(mixed) == 8
+    say(f"  at most {srv.peak_in_flight} requests in flight")
+    assert srv.peak_in_flight > 1
     for r in reqs:
         alone = srv.run([r], realtime=False)[0]
         m = mixed[r.rid]
