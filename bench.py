@@ -75,8 +75,8 @@ def algorithmic_bytes(name: str, n, N, G, k, nh, sort_bytes, sort_launches):
         return 20.0 * N + 24.0 * G         # label, start index, len, inc in; sums out
     if name == "k_col_greedy":
         return 56.0 * G
-    if name == "k_gather":
-        return 60.0 * N                    # perm, random 16-byte record in; 6 sorted arrays out
+    if name == "k_bucket_local":
+        return 60.0 * N                    # index, its 16-byte record in; 6 sorted arrays (40 B) out
     if name == "k_key":
         return 40.0 * N                    # len, inc in; key, index, record out
     if name == "k_encode" or name.startswith("k_encode<"):
@@ -84,7 +84,11 @@ def algorithmic_bytes(name: str, n, N, G, k, nh, sort_bytes, sort_launches):
     if name == "k_recon":                 # symbols, lhat; output points written, originals read for the SSE
         return 12.0 * N + 16.0 * nh
     if name == "k_remap":
-        return 24.0 * N
+        return 24.0 * N                    # index, local start, start map in; symbol scattered out
+    if name == "k_remap_scatter":
+        return 16.0 * N                    # (index, symbol) pairs in; symbol out
+    if name == "k_remap_pairs":
+        return 24.0 * N                    # index, local start in; (index, symbol) pairs out
     if name == "k_compact":
         return 24.0 * N
     if name.startswith("k_sum_leaves"):

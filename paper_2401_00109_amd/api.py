@@ -165,13 +165,13 @@ class Dictionary:
 
 
 def digitize_stats(workspace: torch.Tensor, max_pieces: int, B: int, stream=None) -> dict:
-    """N, G (Stage I starting points), k, active radix passes, Stage II groups and the
-    bytes per piece the radix passes moved, for the last digitize on this workspace."""
-    arr = (C.c_int64 * 6)()
+    """N, G (Stage I starting points), k, active radix passes, Stage II groups, the bytes per piece
+    the radix passes moved and the pieces of oversized prefix groups, for the last digitize on this workspace."""
+    arr = (C.c_int64 * 7)()
     L.check(L.lib().jabba_digitize_stats(_p(workspace), int(max_pieces), int(B), _stream(stream), arr),
             "jabba_digitize_stats")
     return {"N": arr[0], "G": arr[1], "k": arr[2], "sort_passes": arr[3], "stage2_groups": arr[4],
-            "sort_bytes": arr[5]}
+            "sort_bytes": arr[5], "sort_large": arr[6]}
 
 
 def workspace_status(ws: torch.Tensor, stream=None) -> int:

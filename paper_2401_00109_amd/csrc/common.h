@@ -213,7 +213,18 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
 // expected far below n_max (the passes then run persistent workgroups
 // instead of one per possible tile).
 // `tag` suffixes the timing names of the pass kernels ("" for the main sort).
+// prefix_digits > 0: only the highest prefix_digits digits below the top
+// non-constant one are sorted; the pairs leave grouped by
+// (key - kmin) >> ctl[kSortCtlPrefixShift], in input order within a group
+// (with keep_keys false, the values alone).
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st,
-                     const char *tag = "", bool keep_keys = true, bool sparse = false);
+                     const char *tag = "", bool keep_keys = true, bool sparse = false, int prefix_digits = 0);
+// ctl words a consumer of the sort reads: [0] the buffer holding the result,
+// [kSortCtlSkip + d] pass d skipped, [kSortCtlError] a look-back wait ran out,
+// [kSortCtlPrefixShift] the prefix shift of a prefix sort.
+constexpr int kSortCtlSkip = 1;
+constexpr int kSortCtlError = 32;
+constexpr int kSortCtlPrefixShift = 56;
+constexpr int kSortCtlFirst = 57;  // first pass that moves data, 8 when none does
 
 }  // namespace jabba

@@ -3,15 +3,18 @@
 //
 // Data flow (N pieces, all counts stay on the device):
 //   len/inc (canonical) --sum passes--> sigma_len, sigma_inc
-//   --k_key--> (key bits, index), piece records --radix sort--> sorted order (perm)
-//   --k_gather--> sorted arrays key/x/y/len/inc (contiguous for Stage I)
+//   --k_key--> (key bits, index), piece records --radix passes over the
+//       highest four varying digits--> pieces grouped by key prefix
+//       --k_bucket_local (+ fallback for large groups)--> sorted arrays
+//       key/x/y/len/inc/index (contiguous for Stage I)
 //   --k_cuts--> blocks of B sorted pieces, cuts moved past equal keys
 //   --k_stage1 (one wavefront per block)--> local start per piece, start flags,
 //       per-start partial sums (count, len, inc)
 //   --scan + k_compact_starts--> S: starting points in sorted order
 //   --k_stage2--> global start per element of S, partial sums per global group
-//   --scan--> symbol numbers; k_dict writes the dictionary; k_remap sends
-//   each piece's symbol back to canonical order (label propagation).
+//   --scan--> symbol numbers; k_dict writes the dictionary; k_remap_pairs,
+//   one radix pass and k_remap_scatter send each piece's symbol back to
+//   canonical order (label propagation).
 //
 // Decisions use binary64 with no contraction, in the order of the sequential
 // definition, so local starts, blocks and symbols are bit-identical to it.
@@ -41,6 +44,7 @@ struct DigState {
     int64_t n;  // live piece count (clamped)
     int64_t sort_passes;  // radix passes of the main sort that moved data
     int64_t sort_bytes;   // bytes per pair those passes read and wrote
+    int64_t sort_large;   // pieces in prefix groups too large for the local sort
 };
 
 __global__ void k_dig_prepare(DigState *ds, const int64_t *n_dev, int64_t n_max) {
@@ -299,39 +303,275 @@ __global__ void k_key(const int32_t *__restrict__ len, const double *__restrict_
     }
 }
 
-// Pieces in sorted order.  The main sort leaves the order only (no sorted
-// keys), so the key is evaluated again from the piece.
+// ------------------------------------------------------------ bucket sort
+//
+// The radix passes order the pieces by the highest 32 varying bits of
+// key - kmin only (the prefix), keeping canonical order inside a prefix
+// group; they carry the order alone (canonical indices).  The order by
+// (key, index) is finished per group: a workgroup takes the groups that
+// start in its tile of kBucketTile positions, reads their piece records by
+// index once and evaluates their keys again (with the key kernel's own
+// function, so they are the keys sorted on), holds records, keys and indices
+// in LDS (with the rest of the tile's last group, up to kBucketCap positions
+// beyond the tile), and places each member at its group's start plus the
+// number of members with a smaller (key, index), each lane ranking one
+// piece.  Groups are contiguous and ordered by prefix, so this is the full
+// order.  The sorted pieces then leave coalesced: key, x, y, len, inc and
+// the canonical index.  A group that crosses the tile's end and reaches more
+// than kBucketCap beyond its start (at most one per tile) is left to the
+// fallback below, which sorts all such groups together with the general
+// radix sort.
+constexpr int kBucketTile = 1024;
+constexpr int kBucketCap = 256;  // largest tail group finished locally (groups inside a tile always are)
+constexpr int kBucketThreads = 256;
+constexpr int kBucketSpan = kBucketTile + kBucketCap;
+constexpr int kBucketExt = 64;  // positions past the tile read at a time while looking for the next group
+
+__device__ __forceinline__ uint64_t prefix_of(uint64_t k, uint64_t kmin, int shift) {
+    return shift >= 64 ? 0ull : (k - kmin) >> shift;
+}
+
+// key bits of the piece with canonical index c (as k_key computed them)
 template <int Key>
-__global__ void k_gather(const PieceRec *__restrict__ rec, DigState *ds, double scl,
-                         const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
-                         double *__restrict__ sk, double *__restrict__ sx, double *__restrict__ sy,
-                         int32_t *__restrict__ slen, double *__restrict__ sinc, uint32_t *__restrict__ perm) {
+__device__ __forceinline__ uint64_t piece_key_bits(const PieceRec *__restrict__ rec, uint32_t c, double scl, double sl,
+                                                   double si, double ux, double uy) {
+    const PieceRec r = rec[c];
+    return key_bits(sort_key<Key>(scale_piece(r.len, r.inc, scl, sl, si), ux, uy));
+}
+
+template <int Key>
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_local(
+    const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const PieceRec *__restrict__ rec,
+    const int32_t *ctl, const unsigned long long *__restrict__ kmin_p, DigState *ds, double scl,
+    double *__restrict__ sk, double *__restrict__ sx, double *__restrict__ sy, int32_t *__restrict__ slen,
+    double *__restrict__ sinc, uint32_t *__restrict__ perm, int64_t *__restrict__ thead,
+    int64_t *__restrict__ tlarge) {
+    __shared__ uint64_t s_k[kBucketSpan + 1];  // keys of [b0 - 1, b1 + extension)
+    __shared__ double s_inc[kBucketSpan + 1];  // their records and indices
+    __shared__ int32_t s_len[kBucketSpan + 1];
+    __shared__ uint32_t s_v[kBucketSpan + 1];
+    __shared__ uint16_t s_slot[kBucketSpan];   // element of each sorted slot
+    __shared__ unsigned long long s_red[3];
     const int64_t n = ds->n;
-    const double sl = ds->sigma_len, si = ds->sigma_inc;
-    const double ux = Key == kKeyPca ? ds->axis[0] : 0.0, uy = Key == kKeyPca ? ds->axis[1] : 0.0;
-    const uint32_t *vs = ctl[0] ? v1 : v0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    if (t == 0 && tid == 0) {
         int64_t act = 0, bytes = 0;
         for (int d = 0; d < 8; ++d) {
-            if (ctl[1 + d]) continue;
+            if (ctl[kSortCtlSkip + d]) continue;
             act += 1;
             bytes += sort_pass_bytes(ctl[kSortCtlMode + d]);
         }
         ds->sort_passes = act;
         ds->sort_bytes = bytes;
-        if (ctl[32]) set_status(ds->status, kStInternal);  // a radix look-back wait ran out
+        if (ctl[kSortCtlError]) set_status(ds->status, kStInternal);  // a radix look-back wait ran out
     }
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = vs[p];
+    const int64_t b0 = t * kBucketTile;
+    if (b0 >= n) {
+        if (tid == 0) {
+            thead[t] = -1;
+            tlarge[t] = -1;
+        }
+        return;
+    }
+    const int64_t b1 = b0 + kBucketTile < n ? b0 + kBucketTile : n;
+    const int64_t e_lim = b1 + kBucketCap < n ? b1 + kBucketCap : n;
+    const uint32_t *V = ctl[0] ? v1 : v0;
+    const uint64_t kmin = *kmin_p;
+    const int shift = ctl[kSortCtlPrefixShift];
+    const double sl = ds->sigma_len, si = ds->sigma_inc;
+    const double ux = Key == kKeyPca ? ds->axis[0] : 0.0, uy = Key == kKeyPca ? ds->axis[1] : 0.0;
+    // position p is at slot p - b0 + 1; slot 0 holds the position before the
+    // tile (or a copy of position 0 for the first tile, which starts a group)
+    auto fetch = [&](int64_t p, int slot) {
+        const uint32_t c = V[p];
         const PieceRec r = rec[c];
-        const int32_t l = r.len;
-        const double ic = r.inc;
-        const Scaled s = scale_piece(l, ic, scl, sl, si);
-        sk[p] = sort_key<Key>(s, ux, uy);
-        sx[p] = s.x;
-        sy[p] = s.y;
-        slen[p] = l;
-        sinc[p] = ic;
+        s_v[slot] = c;
+        s_len[slot] = r.len;
+        s_inc[slot] = r.inc;
+        s_k[slot] = key_bits(sort_key<Key>(scale_piece(r.len, r.inc, scl, sl, si), ux, uy));
+    };
+    for (int64_t p = (b0 > 0 ? b0 - 1 : 0) + tid; p < b1; p += kBucketThreads) fetch(p, (int)(p - b0) + 1);
+    if (tid == 0) {
+        if (b0 == 0) fetch(0, 0);
+        s_red[0] = ~0ull;
+        s_red[1] = 0ull;
+        s_red[2] = ~0ull;
+    }
+    __syncthreads();
+    auto pre = [&](int slot) -> uint64_t { return prefix_of(s_k[slot], kmin, shift); };
+    auto head = [&](int64_t p) -> bool {
+        const int i = (int)(p - b0) + 1;
+        return p == 0 || pre(i) != pre(i - 1);
+    };
+    // first and last group start in the tile: one LDS atomic per wavefront
+    for (int64_t p0 = b0; p0 < b1; p0 += kBucketThreads) {
+        const int64_t p = p0 + tid;
+        const uint64_t bm = __ballot(p < b1 && head(p));
+        if (bm && lane == 0) {
+            const int64_t wb = p0 + (tid & ~(kWave - 1));
+            atomicMin(&s_red[0], (unsigned long long)(wb + __builtin_ctzll(bm)));
+            atomicMax(&s_red[1], (unsigned long long)(wb + 63 - __builtin_clzll(bm) + 1));
+        }
+    }
+    __syncthreads();
+    if (s_red[1] == 0) {  // no group starts here: the tile lies inside an earlier group
+        if (tid == 0) {
+            thead[t] = -1;
+            tlarge[t] = -1;
+        }
+        return;
+    }
+    // the next group start after the tile: read kBucketExt positions at a time
+    int64_t ext = b1;
+    while (ext < e_lim && s_red[2] == ~0ull) {
+        const int64_t x1 = ext + kBucketExt < e_lim ? ext + kBucketExt : e_lim;
+        if (tid < x1 - ext) fetch(ext + tid, (int)(ext + tid - b0) + 1);
+        __syncthreads();
+        if (tid < kWave) {
+            const int64_t p = ext + tid;
+            const uint64_t bm = __ballot(p < x1 && head(p));
+            if (bm && tid == 0) s_red[2] = (unsigned long long)(ext + __builtin_ctzll(bm));
+        }
+        ext = x1;
+        __syncthreads();
+    }
+    const int64_t lo = (int64_t)s_red[0];
+    const int64_t s_last = (int64_t)s_red[1] - 1;
+    // end of the last group: the next start, n, or beyond the cap (large)
+    const int64_t e = s_red[2] != ~0ull ? (int64_t)s_red[2] : (e_lim == n ? n : INT64_MAX);
+    const bool large = e == INT64_MAX || e - s_last > kBucketCap;
+    const int64_t hi = large ? s_last : e;
+    if (tid == 0) {
+        thead[t] = lo;
+        tlarge[t] = large ? s_last : -1;
+    }
+    const int m = (int)(hi - lo);
+    if (m <= 0) return;
+    const int ofs = (int)(lo - b0) + 1;  // slot of range element 0
+    // rank inside the group by (key, index): each lane finds its group's
+    // bounds by walking to the neighbours with another prefix (groups hold
+    // one or two pieces on average), then counts the smaller members
+    for (int i = tid; i < m; i += kBucketThreads) {
+        const uint64_t pi = pre(ofs + i);
+        int a = i, b = i + 1;
+        while (a > 0 && pre(ofs + a - 1) == pi) --a;
+        while (b < m && pre(ofs + b) == pi) ++b;
+        const uint64_t ki = s_k[ofs + i];
+        const uint32_t vi = s_v[ofs + i];
+        int r = a;
+        for (int q = a; q < b; ++q) {
+            const uint64_t kq = s_k[ofs + q];
+            r += (kq < ki || (kq == ki && s_v[ofs + q] < vi)) ? 1 : 0;
+        }
+        s_slot[r] = (uint16_t)i;
+    }
+    __syncthreads();
+    for (int j = tid; j < m; j += kBucketThreads) {
+        const int i = ofs + s_slot[j];
+        const int32_t len = s_len[i];
+        const double inc = s_inc[i];
+        const Scaled sc = scale_piece(len, inc, scl, sl, si);
+        const int64_t p = lo + j;
+        sk[p] = key_of_bits(s_k[i]);
+        sx[p] = sc.x;
+        sy[p] = sc.y;
+        slen[p] = len;
+        sinc[p] = inc;
+        perm[p] = s_v[i];
+    }
+}
+
+// Fallback plan, one workgroup: the large group recorded by tile t ends at
+// the first group start of a later tile (or n); lsize[t] its size (0 when
+// none); an exclusive scan of lsize (separate launch) gives each group's
+// offset among all large-group pieces.
+__global__ __launch_bounds__(1024) void k_large_plan(const int64_t *__restrict__ thead,
+                                                     const int64_t *__restrict__ tlarge, const DigState *ds,
+                                                     int64_t ntiles_max, int64_t *__restrict__ lsize) {
+    const int64_t n = ds->n;
+    const int64_t ntiles = (n + kBucketTile - 1) / kBucketTile;
+    for (int64_t t = threadIdx.x; t < ntiles_max; t += blockDim.x) {
+        int64_t sz = 0;
+        if (t < ntiles && tlarge[t] >= 0) {
+            int64_t e = n;
+            for (int64_t u = t + 1; u < ntiles; ++u)
+                if (thead[u] >= 0) {
+                    e = thead[u];
+                    break;
+                }
+            sz = e - tlarge[t];
+        }
+        lsize[t] = sz;
+    }
+}
+
+// j-th piece (in prefix-sorted position order) of the large groups: its position
+__device__ __forceinline__ int64_t large_position(int64_t j, const int64_t *__restrict__ loff,
+                                                  const int64_t *__restrict__ tlarge, int64_t ntiles) {
+    int64_t a = 0, b = ntiles;  // last tile with loff[t] <= j
+    while (b - a > 1) {
+        const int64_t mid = (a + b) >> 1;
+        if (loff[mid] <= j)
+            a = mid;
+        else
+            b = mid;
+    }
+    return tlarge[a] + (j - loff[a]);
+}
+
+// pieces of the large groups -> (key, prefix-sorted position) pairs for the general sort
+template <int Key>
+__global__ void k_large_collect(const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
+                                const PieceRec *__restrict__ rec, const int32_t *ctl, const int64_t *__restrict__ loff,
+                                const int64_t *__restrict__ tlarge, const DigState *ds, double scl,
+                                uint64_t *__restrict__ okey, uint32_t *__restrict__ opos, int64_t *__restrict__ n_large) {
+    const int64_t n = ds->n;
+    const int64_t ntiles = (n + kBucketTile - 1) / kBucketTile;
+    const int64_t total = ntiles > 0 ? loff[ntiles] : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_large = total;
+    const uint32_t *V = ctl[0] ? v1 : v0;
+    const double sl = ds->sigma_len, si = ds->sigma_inc;
+    const double ux = Key == kKeyPca ? ds->axis[0] : 0.0, uy = Key == kKeyPca ? ds->axis[1] : 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = large_position(j, loff, tlarge, ntiles);
+        okey[j] = piece_key_bits<Key>(rec, V[p], scl, sl, si, ux, uy);
+        opos[j] = (uint32_t)p;
+    }
+}
+
+// the large groups' pieces, sorted by (key, position) = (key, index), leave
+// into the large groups' positions in order
+template <int Key>
+__global__ void k_large_emit(const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
+                             const PieceRec *__restrict__ rec, const int32_t *ctl,
+                             const uint32_t *__restrict__ sp0, const uint32_t *__restrict__ sp1,
+                             const int32_t *sctl, const int64_t *__restrict__ loff,
+                             const int64_t *__restrict__ tlarge, DigState *ds, double scl,
+                             double *__restrict__ sk, double *__restrict__ sx, double *__restrict__ sy,
+                             int32_t *__restrict__ slen, double *__restrict__ sinc, uint32_t *__restrict__ perm) {
+    const int64_t n = ds->n;
+    const int64_t ntiles = (n + kBucketTile - 1) / kBucketTile;
+    const int64_t total = ntiles > 0 ? loff[ntiles] : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ds->sort_large = total;
+        if (sctl[kSortCtlError]) set_status(ds->status, kStInternal);
+    }
+    const uint32_t *V = ctl[0] ? v1 : v0;
+    const uint32_t *SP = sctl[0] ? sp1 : sp0;
+    const double sl = ds->sigma_len, si = ds->sigma_inc;
+    const double ux = Key == kKeyPca ? ds->axis[0] : 0.0, uy = Key == kKeyPca ? ds->axis[1] : 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = large_position(j, loff, tlarge, ntiles);
+        const uint32_t c = V[SP[j]];
+        const PieceRec r = rec[c];
+        const Scaled sc = scale_piece(r.len, r.inc, scl, sl, si);
+        sk[p] = sort_key<Key>(sc, ux, uy);
+        sx[p] = sc.x;
+        sy[p] = sc.y;
+        slen[p] = r.len;
+        sinc[p] = r.inc;
         perm[p] = c;
     }
 }
@@ -912,6 +1152,12 @@ __global__ void k_dict(const int64_t *__restrict__ g_count, const uint32_t *__re
     }
 }
 
+// Label propagation.  Writing each piece's symbol straight to its canonical
+// index is a random 4-byte scatter over the whole symbol array; that is fast
+// while the array stays in the caches (k_remap).  For larger arrays the
+// (index, symbol) pairs of sorted positions are first grouped by the index's
+// two highest digits with two radix passes, and the scatter then writes one
+// window of 2^16 consecutive indices at a time.
 __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, const int32_t *__restrict__ lab,
                         const uint32_t *__restrict__ sidx, const int32_t *__restrict__ glab,
                         const uint32_t *__restrict__ gsym, int32_t *__restrict__ symbols) {
@@ -920,6 +1166,48 @@ __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, c
         const uint32_t g = sidx[lab[p]];
         symbols[perm[p]] = (int32_t)gsym[glab[g]];
     }
+}
+
+__global__ void k_remap_pairs(const DigState *ds, const uint32_t *__restrict__ perm, const int32_t *__restrict__ lab,
+                              const uint32_t *__restrict__ sidx, const int32_t *__restrict__ glab,
+                              const uint32_t *__restrict__ gsym, uint64_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals) {
+    const int64_t n = ds->n;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = sidx[lab[p]];
+        keys[p] = perm[p];
+        vals[p] = gsym[glab[g]];
+    }
+}
+
+// The keys are a permutation of 0..n-1, so the digit histograms the radix
+// pass plans with follow from n alone: digit d takes the value b on
+// (n / 256^(d+1)) * 256^d + clamp(n mod 256^(d+1) - b * 256^d, 0, 256^d)
+// keys.  Smallest key 0.
+__global__ void k_remap_hist(const DigState *ds, uint32_t *__restrict__ ghist, unsigned long long *__restrict__ kmin) {
+    const uint64_t n = (uint64_t)ds->n;
+    if (threadIdx.x == 0) *kmin = 0ull;
+    const uint64_t b = threadIdx.x;
+    for (int d = 0; d < 8; ++d) {
+        const uint64_t S = d < 7 ? (1ull << (8 * d)) : (1ull << 56);
+        const bool full = d == 7;  // 256^8 exceeds every count
+        const uint64_t P = full ? 0ull : (S << 8);
+        const uint64_t cycles = full ? 0ull : n / P;
+        const uint64_t rem = full ? n : n % P;
+        const uint64_t lo = b * S;
+        const uint64_t part = rem > lo ? (rem - lo < S ? rem - lo : S) : 0ull;
+        ghist[d * 256 + b] = (uint32_t)(cycles * S + part);
+    }
+}
+
+__global__ void k_remap_scatter(const DigState *ds, const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+                                const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
+                                int32_t *__restrict__ symbols) {
+    const int64_t n = ds->n;
+    const uint64_t *K = ctl[0] ? k1 : k0;
+    const uint32_t *V = ctl[0] ? v1 : v0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        symbols[K[q]] = (int32_t)V[q];
 }
 
 // ------------------------------------------------------------ raw 2-D points
@@ -1173,6 +1461,8 @@ struct DigWs {
     double *tree[2];
     unsigned long long *lpart;
     SortBuffers sb;
+    SortBuffers sb2;  // the bucket sort's fallback for large prefix groups
+    int64_t *thead, *tlarge, *lsize, *loff, *n_large;
     double *sk, *sx, *sy, *sinc;
     int32_t *slen;
     uint32_t *perm;
@@ -1217,6 +1507,13 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     w.tree[1] = c.take<double>((t0 + kTreeLeaves - 1) / kTreeLeaves + 1);
     w.lpart = c.take<unsigned long long>(2 * t0 + 2);
     sort_workspace(N, c, &w.sb);
+    sort_workspace(N, c, &w.sb2);
+    const int64_t ntiles = (N + kBucketTile - 1) / kBucketTile;
+    w.thead = c.take<int64_t>(ntiles);
+    w.tlarge = c.take<int64_t>(ntiles);
+    w.lsize = c.take<int64_t>(ntiles);
+    w.loff = c.take<int64_t>(ntiles + 1);
+    w.n_large = c.take<int64_t>(1);
     w.sk = c.take<double>(N);
     w.sx = c.take<double>(N);
     w.sy = c.take<double>(N);
@@ -1254,7 +1551,7 @@ DigWs carve_digitize(void *ws, int64_t max_pieces, int64_t B) {
     w.own = c.take<int32_t>(N);
     w.oflag = c.take<uint32_t>(N);
     w.sblk = c.take<int32_t>(N);
-    w.scan_ws = c.take<char>(scan_workspace(N + 1));
+    w.scan_ws = c.take<char>(scan_workspace(N + 1 > ntiles + 1 ? N + 1 : ntiles + 1));
     w.bytes = c.bytes();
     return w;
 }
@@ -1302,6 +1599,62 @@ extern "C" int jabba_digitize_workspace(int64_t max_pieces, int32_t B, size_t *b
 
 namespace jabba {
 namespace {
+
+constexpr int kPrefixDigits = 4;  // radix digits of the main sort; the rest is sorted per prefix group
+
+// After the prefix passes: the local sort of every prefix group, and the
+// general radix sort of the pieces in groups too large for it.
+template <int Key>
+int bucket_sort(const DigWs &w, int64_t N, double scl, hipStream_t st) {
+    const int64_t ntiles = (N + kBucketTile - 1) / kBucketTile;
+    JB_LAUNCH_NAMED("k_bucket_local", k_bucket_local<Key>, dim3((unsigned)ntiles), dim3(kBucketThreads), 0, st,
+                    w.sb.vals[0], w.sb.vals[1], w.rec, w.sb.ctl, w.sb.kmin, w.ds, scl, w.sk, w.sx, w.sy, w.slen,
+                    w.sinc, w.perm, w.thead, w.tlarge);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_large_plan, dim3(1), dim3(1024), 0, st, w.thead, w.tlarge, w.ds, ntiles, w.lsize);
+    JB_LAUNCH_CHECK();
+    int rc = scan_i64_to_i64(w.lsize, w.loff, nullptr, ntiles, w.scan_ws, st);
+    if (rc) return rc;
+    rc = radix_sort_init(w.sb2, st);
+    if (rc) return rc;
+    JB_LAUNCH_NAMED("k_large_collect", k_large_collect<Key>, dim3(grid_for(N, 4)), dim3(256), 0, st, w.sb.vals[0],
+                    w.sb.vals[1], w.rec, w.sb.ctl, w.loff, w.tlarge, w.ds, scl, w.sb2.keys[0], w.sb2.vals[0],
+                    w.n_large);
+    JB_LAUNCH_CHECK();
+    rc = radix_global_hist(w.sb2, w.n_large, N, st);
+    if (rc) return rc;
+    rc = radix_sort_pairs(w.sb2, w.n_large, N, st, "large", /*keep_keys=*/false, /*sparse=*/true);
+    if (rc) return rc;
+    JB_LAUNCH_NAMED("k_large_emit", k_large_emit<Key>, dim3(grid_for(N, 4)), dim3(256), 0, st, w.sb.vals[0],
+                    w.sb.vals[1], w.rec, w.sb.ctl, w.sb2.vals[0], w.sb2.vals[1], w.sb2.ctl, w.loff, w.tlarge, w.ds,
+                    scl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
+
+// label propagation (symbols in canonical order), see k_remap_pairs
+constexpr int64_t kRemapDirectMax = (int64_t)1 << 26;  // 256 MB of symbols
+
+int remap(const DigWs &w, int64_t N, int32_t *symbols, hipStream_t st) {
+    if (N <= kRemapDirectMax) {
+        JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, symbols);
+        JB_LAUNCH_CHECK();
+        return JABBA_OK;
+    }
+    int rc = radix_sort_init(w.sb, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_remap_pairs, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym,
+              w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_remap_hist, dim3(1), dim3(256), 0, st, w.ds, w.sb.ghist, w.sb.kmin);
+    JB_LAUNCH_CHECK();
+    rc = radix_sort_pairs(w.sb, &w.ds->n, N, st, "remap", /*keep_keys=*/true, /*sparse=*/false, /*prefix_digits=*/2);
+    if (rc) return rc;
+    JB_LAUNCH(k_remap_scatter, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
+              w.sb.vals[1], w.sb.ctl, symbols);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
+}
 
 int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces, int64_t max_pieces, double alpha,
                   double scl, int32_t B, const jabba_tuning *tuning, int32_t *symbols, const jabba_dict *dict,
@@ -1368,15 +1721,13 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     const int64_t *n_live = &w.ds->n;
     rc = radix_global_hist(w.sb, n_live, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, n_live, N, st, "", /*keep_keys=*/false);
+    // radix passes over the highest four varying digits (the order alone),
+    // then every prefix group is put in (key, index) order and leaves as the
+    // sorted arrays
+    rc = radix_sort_pairs(w.sb, n_live, N, st, "", /*keep_keys=*/false, /*sparse=*/false, kPrefixDigits);
     if (rc) return rc;
-    if (key_kind == kKeyPca)
-        JB_LAUNCH_NAMED("k_gather_pca", (k_gather<kKeyPca>), dim3(grid_for(N)), dim3(256), 0, st, w.rec, w.ds, scl,
-                        w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
-    else
-        JB_LAUNCH_NAMED("k_gather", (k_gather<kKeyNorm>), dim3(grid_for(N)), dim3(256), 0, st, w.rec, w.ds, scl,
-                        w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.sk, w.sx, w.sy, w.slen, w.sinc, w.perm);
-    JB_LAUNCH_CHECK();
+    rc = key_kind == kKeyPca ? bucket_sort<kKeyPca>(w, N, scl, st) : bucket_sort<kKeyNorm>(w, N, scl, st);
+    if (rc) return rc;
 
     // Stage I: blocks of B sorted pieces, one wavefront each
     JB_LAUNCH(k_cuts, dim3(grid_for(nblk + 1)), dim3(256), 0, st, w.sk, w.ds, (int64_t)B, nblk, w.cuts);
@@ -1432,8 +1783,8 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     JB_LAUNCH(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen, w.oinc, w.ds,
               scl, *dict);
     JB_LAUNCH_CHECK();
-    JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, symbols);
-    JB_LAUNCH_CHECK();
+    rc = remap(w, N, symbols, st);
+    if (rc) return rc;
     return JABBA_OK;
 }
 
@@ -1522,8 +1873,8 @@ extern "C" int jabba_aggregate_points(const double *x, const double *y, const in
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
-    JB_LAUNCH(k_remap, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, labels);
-    JB_LAUNCH_CHECK();
+    rc = remap(w, N, labels, st);
+    if (rc) return rc;
 
     // centers: labels sorted stably, one wavefront per cluster
     rc = radix_sort_init(w.sb, st);
@@ -1596,6 +1947,7 @@ extern "C" int jabba_digitize_stats(const void *workspace, int64_t max_pieces, i
     JB_HIP(hipMemcpy(&ng, w.n_groups, sizeof(int64_t), hipMemcpyDeviceToHost));
     stats[4] = ng;
     stats[5] = ds.sort_bytes;
+    stats[6] = ds.sort_large;
     return JABBA_OK;
 }
 

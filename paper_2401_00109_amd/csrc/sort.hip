@@ -41,6 +41,8 @@ constexpr int kCtlSrc = 9;     // [9..16]: buffer pass d reads
 constexpr int kCtlError = 32;  // a look-back wait ran out (never expected)
 constexpr int kCtlMode = kSortCtlMode;  // [40..47]: key widths of pass d
 constexpr int kCtlBase = 48;            // bit offset of the 32-bit keys inside key - kmin
+constexpr int kCtlPrefixShift = kSortCtlPrefixShift;  // lowest bit a prefix sort ordered
+constexpr int kCtlFirst = kSortCtlFirst;  // first pass that moves data
 constexpr int kModeIn32 = kSortModeIn32;
 constexpr int kModeOut32 = kSortModeOut32;
 constexpr int kModeNoKeys = kSortModeNoKeys;
@@ -156,32 +158,46 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
 
 // Per digit: skip flag, bucket bases (exclusive scan of the global
 // histogram), the buffer each pass reads and the key widths it moves.  One
-// workgroup of 256.
+// workgroup of 256.  With prefix_digits > 0 only the highest prefix_digits
+// digits below the top non-constant one are sorted (the lower digits are
+// skipped), and ctl[kCtlPrefixShift] receives the lowest sorted bit: the
+// keys then leave grouped by (key - kmin) >> that shift, in input order
+// within a group (64 when no digit varies).
 __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ ghist, const int64_t *n_dev,
-                                                   int64_t n_max, int keep_keys, int32_t *ctl,
+                                                   int64_t n_max, int keep_keys, int prefix_digits, int32_t *ctl,
                                                    uint32_t *__restrict__ gbase) {
     __shared__ uint32_t s_wave[kThreads / kWave];
     __shared__ int s_full;
+    __shared__ int s_const[8];
     const int64_t n = live(n_dev, n_max);
-    int active = 0;
     for (int d = 0; d < 8; ++d) {
         if (threadIdx.x == 0) s_full = 0;
         __syncthreads();
         const uint32_t c = ghist[d * 256 + threadIdx.x];
         if ((int64_t)c == n) s_full = 1;
         gbase[d * 256 + threadIdx.x] = block_excl_scan_256(c, s_wave);
-        const bool skip = s_full != 0 || n <= 1;
-        if (threadIdx.x == 0) {
-            ctl[kCtlSkip + d] = skip ? 1 : 0;
-            ctl[kCtlSrc + d] = active & 1;
-        }
-        active += skip ? 0 : 1;
+        if (threadIdx.x == 0) s_const[d] = (s_full != 0 || n <= 1) ? 1 : 0;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        ctl[kCtlFinal] = active & 1;
+        int top = -1;
+        for (int d = 0; d < 8; ++d)
+            if (!s_const[d]) top = d;
+        const int low = prefix_digits > 0 ? top - prefix_digits + 1 : 0;
+        int active = 0;
         int skip[8], modes[8];
-        for (int d = 0; d < 8; ++d) skip[d] = ctl[kCtlSkip + d];
+        for (int d = 0; d < 8; ++d) {
+            skip[d] = (s_const[d] || d < low) ? 1 : 0;
+            ctl[kCtlSkip + d] = skip[d];
+            ctl[kCtlSrc + d] = active & 1;
+            active += skip[d] ? 0 : 1;
+        }
+        ctl[kCtlFinal] = active & 1;
+        ctl[kCtlPrefixShift] = top < 0 ? 64 : 8 * (low > 0 ? low : 0);
+        int first = 8;
+        for (int d = 7; d >= 0; --d)
+            if (!skip[d]) first = d;
+        ctl[kCtlFirst] = first;
         ctl[kCtlBase] = sort_pass_modes(skip, keep_keys != 0, modes);
         for (int d = 0; d < 8; ++d) ctl[kCtlMode + d] = modes[d];
     }
@@ -460,11 +476,26 @@ int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max,
     return JABBA_OK;
 }
 
+namespace {
+const char *pass_timer_name(const char *tag) {
+    if (!tag || !tag[0]) return "k_onesweep";
+    switch (tag[0]) {
+        case 'g': return "k_onesweep_groups";
+        case 'l': return "k_onesweep_large";
+        case 'p': return "k_onesweep_points";
+        case 'k': return "k_onesweep_kmeans";
+        case 'r': return "k_onesweep_remap";
+        default: return "k_onesweep_other";
+    }
+}
+}  // namespace
+
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag,
-                     bool keep_keys, bool sparse) {
+                     bool keep_keys, bool sparse, int prefix_digits) {
     const bool main_sort = !tag || !tag[0];
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
-    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, keep_keys ? 1 : 0, b.ctl, b.gbase);
+    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, keep_keys ? 1 : 0, prefix_digits, b.ctl,
+              b.gbase);
     // A sparse sort's live count is far below its bound and known only on
     // the device: its passes run persistent workgroups, at most the resident
     // ones (three per compute unit), instead of one workgroup per possible
@@ -474,7 +505,7 @@ int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, 
     JB_LAUNCH_CHECK();
     // the eight passes run back to back and are timed as one group of eight
     // launches, so the per-launch figure carries no event of its own
-    KernelTimer timer(main_sort ? "k_onesweep" : "k_onesweep_groups", st, 8);
+    KernelTimer timer(pass_timer_name(tag), st, 8);
     for (int pass = 0; pass < 8; ++pass) {
         hipLaunchKernelGGL(sparse ? (k_onesweep<1, true>) : main_sort ? (k_onesweep<0, false>) : (k_onesweep<1, false>),
                            dim3((unsigned)(sparse ? grid : tiles)), dim3(kSweepThreads), 0, st, b.keys[0], b.keys[1],

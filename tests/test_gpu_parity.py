@@ -233,6 +233,37 @@ def test_digitize_edge_cases(case):
     assert_centers_close(d, od, inc, od.symbols)
 
 
+@pytest.mark.parametrize("cluster", [0, 900, 1024, 1025, 5000, 60_000])
+def test_digitize_prefix_groups_and_fallback(cluster):
+    """The main sort orders the highest four varying key digits by radix
+    passes and finishes each prefix group locally; a group that crosses a
+    tile's end (1,024 positions) and reaches more than 256 positions past its
+    start goes to the fallback sort.  A cluster of distinct keys within 1e-11
+    relative of each other shares one prefix group, of the cluster's size,
+    among spread pieces."""
+    rng = np.random.default_rng(1000 + cluster)
+    m = 150_000
+    ln = rng.integers(1, 9, m).astype(np.int32)
+    inc = rng.standard_normal(m)
+    if cluster:
+        ln = np.concatenate([ln, np.full(cluster, 3, np.int32)])
+        inc = np.concatenate([inc, 0.5 + 1e-15 * rng.permutation(cluster)])
+        order = rng.permutation(ln.size)
+        ln, inc = ln[order], inc[order]
+    say(f"digitize with a cluster of {cluster} nearly equal keys among {m} pieces")
+    for B in (4096, 97):
+        sym, d, st = gpu_digitize(ln, inc, 0.05, 1.0, B)
+        assert st == 0
+        od = O.digitize(ln, inc, 0.05, 1.0, B)
+        say(f"  B={B}: {d['stats']['sort_passes']} radix passes, {d['stats']['sort_large']} pieces by the fallback")
+        if cluster > 1024:
+            assert d["stats"]["sort_large"] >= cluster
+        assert d["k"] == od.k and d["stats"]["G"] == od.n_starts
+        np.testing.assert_array_equal(sym, od.symbols)
+        np.testing.assert_array_equal(d["center_len"].view(np.uint64), od.center_len.view(np.uint64))
+        assert_centers_close(d, od, inc, od.symbols)
+
+
 @pytest.mark.parametrize("n", [200, 300, 700])
 def test_digitize_long_active_lists(n):
     """Many live Stage I starts at once with separated length columns.  A
