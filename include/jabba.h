@@ -293,11 +293,14 @@ int jabba_axis_tolerances(double alpha_len, double alpha_inc, double scl_in, dou
 /*
  * Counters of the last jabba_digitize that used `workspace` (same max_pieces
  * and B): stats[0] = N pieces, stats[1] = G Stage I starting points,
- * stats[2] = k symbols, stats[3] = radix passes that moved data (digits that
- * are equal in every key are skipped), stats[4] = number of independent groups
- * Stage II ran on, stats[5] = bytes per piece those radix passes read and
- * wrote together (keys narrow to 32 bits once the digits left to sort fit).
- * stats holds 6 entries.
+ * stats[2] = k symbols, stats[3] = radix passes of the global sort that
+ * moved data (the highest four varying digits of the key; digits equal in
+ * every key are skipped), stats[4] = number of independent groups Stage II
+ * ran on, stats[5] = bytes per piece those radix passes read and wrote
+ * together (keys narrow to 32 bits after the first), stats[6] = pieces
+ * whose prefix group was too large for the local sort (sorted by the general
+ * radix sort instead).
+ * stats holds 7 entries.
  * Synchronises `stream`.
  */
 int jabba_digitize_stats(const void *workspace, int64_t max_pieces, int32_t B, void *stream, int64_t *stats);
