@@ -127,7 +127,8 @@ def main() -> int:
                     help="also run a plain 1 GiB copy kernel (for rocprofv3 counter scaling)")
     ap.add_argument("--tuning", default=None, help="JSON dict of jabba_tuning fields")
     ap.add_argument("--pipeline", type=int, default=0,
-                    help="buffer sets in flight (one stream each); 0 = 3 up to 2e8 points, else 1")
+                    help="buffer sets in flight (one stream each); 0 = 3 up to 2e8 points, else 2 (fewer when "
+                         "device memory runs out)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -247,9 +248,20 @@ def measure(w, dev, resident, args, tuning, primary: bool) -> dict:
     # reconstruct, for one batch.  Consecutive steps go to consecutive buffer
     # sets, one stream each, so one batch's compression overlaps the others'
     # digitization and reconstruction; every step still does all of its work.
-    n_sets = args.pipeline if args.pipeline > 0 else (3 if w.n_points <= 200_000_000 else 1)
-    pipe = Pipeline(v, so, t0, w.D, w.tol, w.alpha, w.scl, w.B, N, resident, n_sets=n_sets, tuning=tuning,
-                    max_len=w.max_len)
+    n_sets = args.pipeline if args.pipeline > 0 else (3 if w.n_points <= 200_000_000 else 2)
+    while True:
+        try:
+            pipe = Pipeline(v, so, t0, w.D, w.tol, w.alpha, w.scl, w.B, N, resident, n_sets=n_sets, tuning=tuning,
+                            max_len=w.max_len)
+            break
+        except torch.OutOfMemoryError:
+            if n_sets == 1:
+                raise
+            pipe = None
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            log(f"{n_sets} buffer sets do not fit in device memory; trying {n_sets - 1}")
+            n_sets -= 1
     sets = pipe.sets
     S0 = sets[0]
     sz, full, enc, rec = S0.sz, S0.pieces, S0.enc, S0.rec

@@ -42,7 +42,9 @@ class Pipeline:
     compression itself gets the worst-case capacity sum(n_s - 1).  resident:
     the dictionary the encode step uses.  The constructor compresses and
     digitizes the batch once on each set (current stream) and runs the
-    reconstruction's size pass, which synchronises, to allocate its output."""
+    reconstruction's size pass, which synchronises, to allocate its output.
+    The sets all hold the same batch, so the first set's symbol count sizes
+    the dictionaries of the others."""
 
     def __init__(self, values: torch.Tensor, series_off: torch.Tensor, t0: torch.Tensor, D: int, tol: float,
                  alpha: float, scl: float, B: int, max_pieces: int, resident: api.Dictionary, n_sets: int = 3,
@@ -57,9 +59,10 @@ class Pipeline:
         n_points = values.numel()
         cap = max(n_points, 1)
         self.sets: list[BufferSet] = []
-        for _ in range(n_sets):
+        capacity = self.max_pieces
+        for i in range(n_sets):
             sz = api.Symbolizer(n_series, n_points, D, tol, alpha, scl, B, max_len=max_len,
-                                max_pieces=self.max_pieces, capacity=self.max_pieces, tuning=tuning, device=dev)
+                                max_pieces=self.max_pieces, capacity=capacity, tuning=tuning, device=dev)
             full = api.Pieces(torch.empty(cap, dtype=torch.int32, device=dev),
                               torch.empty(cap, dtype=torch.float64, device=dev),
                               sz.pieces.piece_off, sz.pieces.n_pieces, cap)
@@ -68,9 +71,12 @@ class Pipeline:
             sz.compress(values, series_off)
             sz.digitize()
             rec.size(sz.symbols, sz.dictionary)
-            self.sets.append(BufferSet(sz, full, torch.empty(cap, dtype=torch.int32, device=dev), rec,
+            self.sets.append(BufferSet(sz, full, torch.empty(self.max_pieces, dtype=torch.int32, device=dev), rec,
                                        torch.cuda.Stream(device=dev),
                                        api._ws(api.encode_workspace_bytes(resident.capacity), dev)))
+            # every set digitizes the same batch: the first set's symbol count
+            # sizes the other sets' dictionaries
+            capacity = max(sz.dictionary.size(), 1)
 
     def step(self, S: BufferSet):
         """Enqueue one full step on set S's stream."""
