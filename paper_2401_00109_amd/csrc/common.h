@@ -10,6 +10,10 @@
 namespace jabba {
 
 constexpr int kWave = 64;
+// The chip's accelerator dies (XCDs), each with its own L2.  The dispatcher
+// hands workgroups to them round robin, so blockIdx.x % kXcds names the
+// workgroup's XCD (a performance assumption only: no result depends on it).
+constexpr int kXcds = 8;
 
 // Device status bits (OR-ed into the first word of a workspace).
 enum : int32_t {

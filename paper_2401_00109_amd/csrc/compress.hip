@@ -511,6 +511,190 @@ __global__ __launch_bounds__(1024) void k_compress(const double *__restrict__ t,
     }
 }
 
+// One lane per domain (W = 1) with refills on a common schedule.  A lane's
+// round tests one candidate c and needs one point it has not read before:
+// point s + c - 1 (the new term of the sums) was the previous round's end
+// point, and whether the candidate is accepted (c + 1) or ends the piece at
+// c - 1 (the next piece starts there, at its c = 2), the next round's end
+// point is the one after this round's.  So every lane takes exactly one new
+// point per round, and all lanes of the wavefront refill their rings at the
+// same rounds, every kQ1 rounds, each with the kQ1 points it loaded (one
+// cache line) at the refill before.  Those loads are a whole refill period
+// old when they are stored, where a per-lane refill schedule makes the
+// wavefront wait on whichever lane refilled last.  A lane that starts a
+// domain stages its first points itself, sized so that it falls into step
+// with the schedule.  The arithmetic, the certified filter and the exact
+// evaluation are those of k_compress with W = 1.
+constexpr int kR1 = 32;           // ring of staged points per lane
+constexpr int kQ1 = kR1 / 2;      // points per refill, and rounds between refills
+
+size_t compress1_lds_per_wave() { return (size_t)kWave * (kR1 + 1) * sizeof(double); }
+
+template <bool Norm>
+__global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t, const Dom *__restrict__ doms,
+                                                    const int32_t *__restrict__ queue,
+                                                    const int64_t *__restrict__ n_dom_p, int32_t *__restrict__ q_head,
+                                                    int64_t direct_base, int64_t direct_end, double tol2,
+                                                    int32_t max_len, int32_t *__restrict__ st_len,
+                                                    double *__restrict__ st_inc, int32_t *__restrict__ dom_count,
+                                                    int32_t *status, const double *__restrict__ zmean,
+                                                    const double *__restrict__ zstd) {
+    extern __shared__ double ring_all[];
+    const int lane = lane_id();
+    // the stride of kR1 + 1 doubles puts the same slot of neighbouring lanes
+    // in different LDS banks
+    double *ring = ring_all + (size_t)threadIdx.x * (kR1 + 1);
+    const int64_t n_dom = *n_dom_p;
+    const bool direct = direct_base >= 0;
+    const int64_t wave_g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+
+    int32_t dom = -1;
+    bool exhausted = false;
+    int64_t s = 0, e = 0, obase = 0;
+    int64_t le = 0;     // the ring holds points [le - kR1, le)
+    int32_t np = 0;
+    int32_t c = 2;
+    double ts = 0.0;    // point s (the piece's start)
+    double tpk = 0.0;   // point s + c - 1
+    double tend = 0.0;  // point s + c (the candidate's end; any value past e)
+    double S2c = 0.0, S1c = 0.0;  // sums over the terms below k = c - 1
+    double zm = 0.0, zs = 1.0;
+    double pre[kQ1];    // points [le, le + kQ1), stored at the next refill
+    uint32_t rr = 0;    // iteration count, the same on every lane
+
+    auto value = [&](int64_t p) -> double {
+        if constexpr (Norm) {
+            const double d = t[p] - zm;
+            return d / zs;
+        } else {
+            return t[p];
+        }
+    };
+    auto at = [&](int64_t p) -> double { return ring[p & (kR1 - 1)]; };
+    auto at_far = [&](int64_t p) -> double { return p >= le - kR1 ? ring[p & (kR1 - 1)] : value(p); };
+    auto load_pre = [&]() {
+#pragma unroll
+        for (int r = 0; r < kQ1; ++r) {
+            const int64_t p = le + r;
+            pre[r] = value(p <= e ? p : e);
+        }
+    };
+    // The round of iteration rr reads point q = s + c + 1, one further each
+    // round; a refill at the start of each iteration with rr % kQ1 == 0
+    // stores pre[] at [le, le + kQ1).  A domain started at iteration rr0 reads
+    // q0 = s + 3 first and meets its first refill k = (kQ1 - rr0 % kQ1) % kQ1
+    // rounds later; staging [q0, q0 + k + kQ1) keeps every q it reads inside
+    // [le - kR1, le) from then on (right after a refill le - q = kR1, just
+    // before one le - q = kQ1 + 1), and a refill overwrites only points below
+    // the next q.
+    auto start_domain = [&](int32_t d) {
+        dom = d;
+        const Dom x = doms[dom];
+        s = x.start;
+        e = x.start + x.nint;
+        obase = x.start;
+        np = 0;
+        if constexpr (Norm) {
+            zm = zmean[x.series];
+            zs = zstd[x.series];
+        }
+        ts = value(s);
+        tpk = value(s + 1);
+        tend = value(s + 2 <= e ? s + 2 : e);
+        if (!isfinite(ts)) set_status(status, kStNonFinite);
+        c = 2;
+        S2c = 0.0;
+        S1c = 0.0;
+        const int k = (int)((kQ1 - (rr & (kQ1 - 1))) & (kQ1 - 1));
+        const int64_t q0 = s + 3;
+        le = q0 + k + kQ1;
+        for (int64_t p = q0; p < le; ++p) ring[p & (kR1 - 1)] = value(p <= e ? p : e);
+        load_pre();
+    };
+
+    if (direct) {
+        exhausted = true;
+        const int64_t d = direct_base + wave_g * kWave + lane;
+        if (d < direct_end && d < n_dom) start_domain((int32_t)d);
+    }
+
+    for (;;) {
+        if (!direct) {
+            const bool need = dom < 0 && !exhausted;
+            const uint64_t nm = ballot(need);
+            if (nm) {
+                const int first = ffs64(nm);
+                int base = 0;
+                if (lane == first) base = atomicAdd(q_head, (int)__popcll(nm));
+                base = shfl_i(base, first);
+                if (need) {
+                    const int64_t qp = (int64_t)base + __popcll(nm & lanemask_lt());
+                    if (qp < n_dom)
+                        start_domain(queue[qp]);
+                    else
+                        exhausted = true;
+                }
+            }
+        }
+        const bool act = dom >= 0;
+        if (ballot(act || !exhausted) == 0ull) break;
+        if ((rr & (kQ1 - 1)) == 0 && act) {
+#pragma unroll
+            for (int r = 0; r < kQ1; ++r) ring[(le + r) & (kR1 - 1)] = pre[r];
+            le += kQ1;
+            load_pre();
+        }
+        ++rr;
+        if (!act) continue;
+
+        // the next round's end point
+        const double tnext = at(s + c + 1);
+        const double d = tpk - ts;
+        const double S2 = d * d + S2c;
+        const double S1 = (double)(c - 1) * d + S1c;
+        int verdict = -1;
+        if ((s + c <= e) && (max_len <= 0 || c <= max_len)) {
+            const double b = (tend - ts) / (double)c;
+            const double thr = (double)(c - 1) * tol2;
+            verdict = filter_decide(S2, S1, b, ts, c, thr);
+            if (verdict == 0) {
+                // undecided by the bound: evaluate the definition itself
+                double acc = 0.0;
+                for (int32_t k = 1; k < c; ++k) {
+                    double v = b * (double)k;
+                    v = ts + v;
+                    const double r = v - at_far(s + k);
+                    acc = acc + r * r;
+                }
+                verdict = (acc <= thr) ? 1 : -1;
+            }
+        }
+        if (verdict < 0) {
+            // the piece ends at the last accepted length, on point s + c - 1
+            const int32_t L = c - 1;
+            if (!isfinite(tpk)) set_status(status, kStNonFinite);
+            st_len[obase + np] = L;
+            st_inc[obase + np] = tpk - ts;
+            ++np;
+            s += L;
+            ts = tpk;
+            c = 2;
+            S2c = 0.0;
+            S1c = 0.0;
+            if (s >= e) {
+                dom_count[dom] = np;
+                dom = -1;
+            }
+        } else {
+            ++c;
+            S2c = S2;
+            S1c = S1;
+        }
+        tpk = tend;
+        tend = tnext;
+    }
+}
+
 // ------------------------------------------------------------ segment repair
 //
 // Segments were compressed as if each were a domain, so every segment's
@@ -708,15 +892,26 @@ int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t 
 template <int W>
 void launch_w(dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
               int64_t dbase, int64_t dend, double tol2, int32_t max_len, const double *zmean, const double *zstd) {
-    const size_t lds = compress_lds_per_wave<W>() * (b.x / kWave);
-    if (zmean)
-        JB_LAUNCH_NAMED("k_compress_znorm", (k_compress<W, true>), g, b, lds, st, t, w.doms, w.queue, n_dom_p,
-                        w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
-                        zstd);
-    else
-        JB_LAUNCH_NAMED("k_compress<W>", (k_compress<W, false>), g, b, lds, st, t, w.doms, w.queue, n_dom_p,
-                        w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
-                        zstd);
+    if constexpr (W == 1) {
+        const size_t lds = compress1_lds_per_wave() * (b.x / kWave);
+        if (zmean)
+            JB_LAUNCH_NAMED("k_compress_znorm", k_compress1<true>, g, b, lds, st, t, w.doms, w.queue, n_dom_p,
+                            w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
+                            zstd);
+        else
+            JB_LAUNCH_NAMED("k_compress<W>", k_compress1<false>, g, b, lds, st, t, w.doms, w.queue, n_dom_p, w.q_head,
+                            dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean, zstd);
+    } else {
+        const size_t lds = compress_lds_per_wave<W>() * (b.x / kWave);
+        if (zmean)
+            JB_LAUNCH_NAMED("k_compress_znorm", (k_compress<W, true>), g, b, lds, st, t, w.doms, w.queue, n_dom_p,
+                            w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
+                            zstd);
+        else
+            JB_LAUNCH_NAMED("k_compress<W>", (k_compress<W, false>), g, b, lds, st, t, w.doms, w.queue, n_dom_p,
+                            w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
+                            zstd);
+    }
 }
 
 int launch_repair(const CompressWs &w, const int64_t *n_dom_p, int64_t n_series, int64_t total_points, int32_t D,
@@ -780,7 +975,7 @@ int32_t segment_of(const jabba_tuning *tuning, int64_t n_series, int64_t total_p
 
 size_t lds_per_wave(int W) {
     switch (W) {
-        case 1: return compress_lds_per_wave<1>();
+        case 1: return compress1_lds_per_wave();
         case 2: return compress_lds_per_wave<2>();
         case 4: return compress_lds_per_wave<4>();
         case 8: return compress_lds_per_wave<8>();
@@ -813,7 +1008,7 @@ int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, cons
 // per domain keeps 64 domains per wavefront: with short pieces most rounds
 // end a piece, so wider groups mostly test candidates past the first failure.
 constexpr int kDefaultW = 1;
-constexpr int kDefaultWavesPerBlock = 2;
+constexpr int kDefaultWavesPerBlock = 4;
 constexpr int kDefaultBlocksPerCu = 4;
 
 }  // namespace jabba
@@ -846,7 +1041,8 @@ extern "C" int jabba_compress(const double *values, const int64_t *series_off, i
     if (wpb < 1 || wpb > 16 || bpc < 1 || bpc > 32) return JABBA_EINVAL;
     if (W != 1 && W != 2 && W != 4 && W != 8 && W != 16 && W != 32 && W != 64) return JABBA_EINVAL;
     // a workgroup's ring buffers stay within 64 KB of LDS
-    const int max_wpb = (int)(65536 / lds_per_wave(W));
+    const size_t lw = lds_per_wave(W);
+    const int max_wpb = lw ? (int)(65536 / lw) : 16;
     if (wpb > max_wpb) wpb = max_wpb < 1 ? 1 : max_wpb;
     const int32_t G = segment_of(tuning, n_series, total_points, D, &rc);
     if (rc) return rc;
@@ -886,7 +1082,8 @@ extern "C" int jabba_compress_znorm(const double *values, const int64_t *series_
     }
     if (wpb < 1 || wpb > 16 || bpc < 1 || bpc > 32) return JABBA_EINVAL;
     if (W != 1 && W != 2 && W != 4 && W != 8 && W != 16 && W != 32 && W != 64) return JABBA_EINVAL;
-    const int max_wpb = (int)(65536 / lds_per_wave(W));
+    const size_t lw = lds_per_wave(W);
+    const int max_wpb = lw ? (int)(65536 / lw) : 16;
     if (wpb > max_wpb) wpb = max_wpb < 1 ? 1 : max_wpb;
     const int32_t G = segment_of(tuning, n_series, total_points, D, &rc);
     if (rc) return rc;

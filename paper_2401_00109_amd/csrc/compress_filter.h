@@ -40,7 +40,10 @@ JB_HD inline int filter_decide(double S2, double S1, double b, double ts, int32_
     // K2 = sum_{k<c} k^2, an exact integer below c = 2^20 (rounded once to
     // double past 2^53; that relative error u is inside the 8u*ME term)
     double K2;
-    if (c <= (1 << 20)) {
+    if (c <= 1024) {  // the product stays below 2^32
+        const uint32_t ci = (uint32_t)c;
+        K2 = (double)((ci - 1u) * ci * (2u * ci - 1u) / 6u);
+    } else if (c <= (1 << 20)) {
         const int64_t ci = c;
         K2 = (double)((ci - 1) * ci * (2 * ci - 1) / 6);
     } else {

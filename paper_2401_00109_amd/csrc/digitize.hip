@@ -392,7 +392,35 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_local(
         s_inc[slot] = r.inc;
         s_k[slot] = key_bits(sort_key<Key>(scale_piece(r.len, r.inc, scl, sl, si), ux, uy));
     };
-    for (int64_t p = (b0 > 0 ? b0 - 1 : 0) + tid; p < b1; p += kBucketThreads) fetch(p, (int)(p - b0) + 1);
+    {
+        // all index loads of the thread first, then all record loads, so
+        // the two dependent round trips overlap across its positions
+        constexpr int kPer = (kBucketTile + kBucketThreads) / kBucketThreads;
+        const int64_t f0 = (b0 > 0 ? b0 - 1 : 0) + tid;
+        uint32_t cs[kPer];
+        PieceRec rs[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t p = f0 + (int64_t)u * kBucketThreads;
+            cs[u] = p < b1 ? V[p] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t p = f0 + (int64_t)u * kBucketThreads;
+            if (p < b1) rs[u] = rec[cs[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t p = f0 + (int64_t)u * kBucketThreads;
+            if (p < b1) {
+                const int slot = (int)(p - b0) + 1;
+                s_v[slot] = cs[u];
+                s_len[slot] = rs[u].len;
+                s_inc[slot] = rs[u].inc;
+                s_k[slot] = key_bits(sort_key<Key>(scale_piece(rs[u].len, rs[u].inc, scl, sl, si), ux, uy));
+            }
+        }
+    }
     if (tid == 0) {
         if (b0 == 0) fetch(0, 0);
         s_red[0] = ~0ull;

@@ -8,8 +8,8 @@
 //    scale 2^52: a wavefront inclusive scan plus a carry from the previous
 //    chunk, then S_j = (C_j + 2^51) >> 52 and len^_j = S_j - S_{j-1}.
 //  * Values: V_j = V_{j-1} + inc~_j is a sequential binary64 recurrence; the
-//    wavefront walks it lane by lane (a uniform running value), so every V_j
-//    has the bits of the plain left-to-right evaluation.
+//    wavefront walks it one lane per step (a DPP shift and one addition), so
+//    every V_j has the bits of the plain left-to-right evaluation.
 //  * Fill: V_{j-1} + (inc~_j / len^_j) * q for 0 < q < len^_j, then V_j.
 #include "common.h"
 
@@ -45,6 +45,33 @@ __device__ __forceinline__ u128 wave_incl_scan_u128(u128 x) {
     x += dpp_u128<0x142, 0xa>(x);
     x += dpp_u128<0x143, 0xc>(x);
     return x;
+}
+
+// lane l receives lane l-1's v and lane 0 receives `first` (DPP wave shift
+// right by one lane; the source of lane 0 is out of range, so it keeps the
+// old value)
+__device__ __forceinline__ double wave_shr1_f64(double v, double first) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(first), __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(first), __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int64_t wave_shr1_i64(int64_t v, int64_t first) {
+    const int lo = __builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(first >> 32), (int)(v >> 32), 0x138, 0xf, 0xf, false);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// value of lane l, l uniform across the wavefront (scalar reads, no LDS)
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ u128 readlane_u128(u128 v, int l) {
+    const uint64_t lo = (uint64_t)readlane_i64((int64_t)(uint64_t)v, l);
+    const uint64_t hi = (uint64_t)readlane_i64((int64_t)(uint64_t)(v >> 64), l);
+    return ((u128)hi << 64) | lo;
 }
 
 __device__ __forceinline__ u128 shfl_u128(u128 v, int l) {
@@ -230,7 +257,7 @@ constexpr int kFillThreads = kReconThreads - kWave;
 // sums its own points in order, and the 64 partials are added by one fixed
 // tree per series (deterministic).
 template <bool Dict>
-__global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t *__restrict__ piece_off,
+__global__ __launch_bounds__(kReconThreads, 8) void k_recon(Src src, const int64_t *__restrict__ piece_off,
                                                          const int64_t *__restrict__ out_off, int64_t n_series,
                                                          const double *__restrict__ t0, double *__restrict__ out,
                                                          int64_t *__restrict__ lhat,
@@ -295,32 +322,38 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(Src src, const int64_t 
                 // inclusive scan of the fixed-point center lengths
                 u128 C = wave_incl_scan_u128(lt) + carryC;
                 const int64_t S = fixed_round(C);
-                int64_t Sp = __shfl_up(S, 1);
-                if (lane == 0) Sp = carryS;
+                const int64_t Sp = wave_shr1_i64(S, carryS);
                 const int64_t lh = S - Sp;
-                // sequential running value: V is uniform across the lanes,
-                // each step adds the next piece's increment (a scalar read
-                // off the add chain) and every lane stores the same V_j
+                // sequential running value, V_j on lane j: every step moves
+                // each lane's value one lane up (lane 0 takes V before the
+                // chunk) and adds the lane's own increment.  After cnt steps
+                // lanes 0..cnt-1 hold V_0..V_{cnt-1}, each the one binary64
+                // addition V_{j-1} + inc~_j of the left-to-right evaluation.
                 const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
                 ReconChunk &B = buf[t & 1];
                 if (lane == 0) B.vin = V;
+                // (prev keeps V on lane 0 from one step to the next, so the
+                // shift writes it in place)
+                double Vl = V, prev = V;
                 int l = 0;
                 for (; l + 4 <= cnt; l += 4) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        V = V + readlane_f64(it, l + u);
-                        B.vme[l + u] = V;
+                        prev = wave_shr1_f64(Vl, prev);
+                        Vl = prev + it;
                     }
                 }
                 for (; l < cnt; ++l) {
-                    V = V + readlane_f64(it, l);
-                    B.vme[l] = V;
+                    prev = wave_shr1_f64(Vl, prev);
+                    Vl = prev + it;
                 }
+                B.vme[lane] = Vl;
+                V = readlane_f64(Vl, cnt - 1);
                 B.beg[lane] = Sp;
                 B.end[lane] = S;
                 B.slope[lane] = it / (double)lh;
-                carryC = shfl_u128(C, cnt - 1);
-                carryS = __shfl(S, cnt - 1);
+                carryC = readlane_u128(C, cnt - 1);
+                carryS = readlane_i64(S, cnt - 1);
             }
             if (!producer && t > 0) {
                 const int64_t tc = t - 1;
@@ -385,19 +418,24 @@ __global__ void k_recon_prep(int32_t *status) {
     if (threadIdx.x == 0) status[0] = 0;
 }
 
+// The grids below hold one wavefront (k_recon_count) or one workgroup
+// (k_recon) per series and no more than that: series lengths can differ by
+// orders of magnitude, and the dispatcher starting each workgroup as an
+// earlier one ends balances the load, where a fixed share of series per
+// workgroup would leave the kernel waiting on the few workgroups that drew the
+// longest series.  (The kernels still stride, so any grid is correct.)
+constexpr int64_t kMaxGrid = ((int64_t)1 << 31) - 1;
+
 unsigned waves_grid(int64_t n_series) {
     int64_t blocks = (n_series * kWave + 255) / 256;
-    const int64_t cap = (int64_t)device_cu_count() * 16;
-    if (blocks > cap) blocks = cap;
+    if (blocks > kMaxGrid) blocks = kMaxGrid;
     if (blocks < 1) blocks = 1;
     return (unsigned)blocks;
 }
 
-// one workgroup per series, at most 16 resident per compute unit
 unsigned series_grid(int64_t n_series) {
     int64_t blocks = n_series;
-    const int64_t cap = (int64_t)device_cu_count() * 16;
-    if (blocks > cap) blocks = cap;
+    if (blocks > kMaxGrid) blocks = kMaxGrid;
     if (blocks < 1) blocks = 1;
     return (unsigned)blocks;
 }

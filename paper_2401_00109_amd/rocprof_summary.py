@@ -10,8 +10,8 @@ WRITE_SIZE, in KiB per dispatch).  Each counter is scaled by what it reads
 for a plain copy kernel of known size that the benchmark launches in the
 same run (``--pmc-calibrate``: torch.neg over 1 GiB, reading and writing
 1 GiB), so the factor corrects the counter's granularity on this device.
-traffic.json records the source hash of the kernels; the benchmark ignores
-it once the kernel sources change.
+traffic_<workload>.json records the source hash of the kernels; the
+benchmark ignores it once the kernel sources change.
 """
 from __future__ import annotations
 
@@ -52,11 +52,11 @@ def timing_name(kernel: str) -> str:
     if not m:
         return kernel.split("(")[0][-60:]
     base, targs = m.group(1), (m.group(2) or "")
-    if base == "k_compress":
+    if base in ("k_compress", "k_compress1"):
         return "k_compress_znorm" if ("true" in targs or "(bool)1" in targs) else "k_compress<W>"
-    if base == "k_onesweep":
-        return base + ("_groups" if targs.startswith("<1") else "")
-    if base in ("k_key", "k_gather"):
+    if base == "k_onesweep":  # <0, ...>: the main sort's passes; the others: every other radix sort
+        return base + ("" if targs.startswith("<0") else "_aux")
+    if base in ("k_key", "k_bucket_local", "k_large_collect", "k_large_emit"):
         return base + ("_pca" if targs == "<1>" else "")
     if base == "k_recon":
         return "k_recon" if ("true" in targs or "(bool)1" in targs) else "k_recon_pieces"
@@ -160,7 +160,7 @@ def main() -> int:
                        "bytes_per_launch": (fb or 0.0) + (wb or 0.0) if (fb is not None and wb is not None) else None}
 
     os.makedirs(args.out, exist_ok=True)
-    with open(os.path.join(args.out, "traffic.json"), "w") as fh:
+    with open(os.path.join(args.out, f"traffic_{args.workload}.json"), "w") as fh:
         json.dump({"source_hash": source_hash(), "workload": args.workload, "fetch_factor": ff, "write_factor": wf,
                    "calibration": "torch.neg over 1 GiB of float64 (1 GiB read + 1 GiB written per launch)",
                    "kernels": traffic}, fh, indent=1, sort_keys=True)
