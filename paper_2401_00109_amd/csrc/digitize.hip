@@ -1184,8 +1184,12 @@ __global__ void k_dict(const int64_t *__restrict__ g_count, const uint32_t *__re
 // index is a random 4-byte scatter over the whole symbol array; that is fast
 // while the array stays in the caches (k_remap).  For larger arrays the
 // (index, symbol) pairs of sorted positions are first grouped by the index's
-// two highest digits with two radix passes, and the scatter then writes one
-// window of 2^16 consecutive indices at a time.
+// highest 16 bits with two radix passes.  The indices are a permutation of
+// 0..n-1, so after the grouping window w of 2^wlog consecutive indices holds
+// exactly its own pairs, at positions [w * 2^wlog, (w + 1) * 2^wlog): one
+// workgroup scatters a window's symbols in LDS and writes the window out in
+// order (k_remap_window), so every line of the symbol array is written once
+// and whole.
 __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, const int32_t *__restrict__ lab,
                         const uint32_t *__restrict__ sidx, const int32_t *__restrict__ glab,
                         const uint32_t *__restrict__ gsym, int32_t *__restrict__ symbols) {
@@ -1196,46 +1200,106 @@ __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, c
     }
 }
 
+// The pairs' key is the canonical index shifted left by `sh` bits, so that
+// the two highest radix digits hold the index's highest 16 bits.
 __global__ void k_remap_pairs(const DigState *ds, const uint32_t *__restrict__ perm, const int32_t *__restrict__ lab,
                               const uint32_t *__restrict__ sidx, const int32_t *__restrict__ glab,
-                              const uint32_t *__restrict__ gsym, uint64_t *__restrict__ keys,
+                              const uint32_t *__restrict__ gsym, int sh, uint64_t *__restrict__ keys,
                               uint32_t *__restrict__ vals) {
     const int64_t n = ds->n;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t g = sidx[lab[p]];
-        keys[p] = perm[p];
+        keys[p] = (uint64_t)perm[p] << sh;
         vals[p] = gsym[glab[g]];
     }
 }
 
-// The keys are a permutation of 0..n-1, so the digit histograms the radix
-// pass plans with follow from n alone: digit d takes the value b on
-// (n / 256^(d+1)) * 256^d + clamp(n mod 256^(d+1) - b * 256^d, 0, 256^d)
-// keys.  Smallest key 0.
-__global__ void k_remap_hist(const DigState *ds, uint32_t *__restrict__ ghist, unsigned long long *__restrict__ kmin) {
+// The keys are {i << sh : 0 <= i < n}, so the digit histograms the radix
+// pass plans with follow from n and sh alone.  Digit d of i << sh is bits
+// [a, a + 8) of i with a = 8d - sh when a >= 0: the value b on
+// (n / 2^(a+8)) * 2^a + clamp(n mod 2^(a+8) - b * 2^a, 0, 2^a) keys.  For
+// -8 < a < 0 the digit is (i mod 2^(8+a)) << -a: each multiple m << -a on
+// (n / 2^(8+a)) + (m < n mod 2^(8+a)) keys, the other values on none; for
+// a <= -8 it is 0 on every key.  Smallest key 0.
+__global__ void k_remap_hist(const DigState *ds, int sh, uint32_t *__restrict__ ghist,
+                             unsigned long long *__restrict__ kmin) {
     const uint64_t n = (uint64_t)ds->n;
     if (threadIdx.x == 0) *kmin = 0ull;
     const uint64_t b = threadIdx.x;
     for (int d = 0; d < 8; ++d) {
-        const uint64_t S = d < 7 ? (1ull << (8 * d)) : (1ull << 56);
-        const bool full = d == 7;  // 256^8 exceeds every count
-        const uint64_t P = full ? 0ull : (S << 8);
-        const uint64_t cycles = full ? 0ull : n / P;
-        const uint64_t rem = full ? n : n % P;
-        const uint64_t lo = b * S;
-        const uint64_t part = rem > lo ? (rem - lo < S ? rem - lo : S) : 0ull;
-        ghist[d * 256 + b] = (uint32_t)(cycles * S + part);
+        const int a = 8 * d - sh;
+        uint64_t cnt;
+        if (a >= 0) {
+            const bool full = a + 8 >= 64;  // 2^(a+8) exceeds every count
+            const uint64_t S = 1ull << a;
+            const uint64_t P = full ? 0ull : (S << 8);
+            const uint64_t cycles = full ? 0ull : n / P;
+            const uint64_t rem = full ? n : n % P;
+            const uint64_t lo = b * S;
+            const uint64_t part = rem > lo ? (rem - lo < S ? rem - lo : S) : 0ull;
+            cnt = cycles * S + part;
+        } else if (a > -8) {
+            const uint64_t P = 1ull << (8 + a);
+            const uint64_t step = 1ull << (-a);
+            cnt = (b % step) ? 0ull : n / P + ((b / step) < n % P ? 1ull : 0ull);
+        } else {  // the digit lies below the shift: 0 on every key
+            cnt = b == 0 ? n : 0ull;
+        }
+        ghist[d * 256 + b] = (uint32_t)cnt;
     }
 }
 
+constexpr int kWindowMaxLog = 14;  // 16,384 symbols: 64 KB of LDS
+constexpr int kWindowThreads = 1024;
+constexpr int kWindowPer = (1 << kWindowMaxLog) / kWindowThreads;
+
+__global__ __launch_bounds__(kWindowThreads) void k_remap_window(DigState *ds, const uint64_t *__restrict__ k0,
+                                                                 const uint64_t *__restrict__ k1,
+                                                                 const uint32_t *__restrict__ v0,
+                                                                 const uint32_t *__restrict__ v1, const int32_t *ctl,
+                                                                 int sh, int wlog, int32_t *__restrict__ symbols) {
+    extern __shared__ int32_t s_sym[];
+    const int64_t n = ds->n;
+    const int64_t w0 = (int64_t)blockIdx.x << wlog;
+    if (w0 >= n) return;
+    const int m = (int)(n - w0 < ((int64_t)1 << wlog) ? n - w0 : ((int64_t)1 << wlog));
+    const uint64_t *K = ctl[0] ? k1 : k0;
+    const uint32_t *V = ctl[0] ? v1 : v0;
+    uint64_t kr[kWindowPer];
+    uint32_t vr[kWindowPer];
+#pragma unroll
+    for (int u = 0; u < kWindowPer; ++u) {
+        const int i = u * kWindowThreads + (int)threadIdx.x;
+        kr[u] = i < m ? K[w0 + i] : 0ull;
+        vr[u] = i < m ? V[w0 + i] : 0u;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < kWindowPer; ++u) {
+        const int i = u * kWindowThreads + (int)threadIdx.x;
+        if (i < m) {
+            const int64_t li = (int64_t)(kr[u] >> sh) - w0;
+            if (li >= 0 && li < m)
+                s_sym[li] = (int32_t)vr[u];
+            else
+                bad = true;  // not a permutation: never expected
+        }
+    }
+    if (bad) set_status(ds->status, kStInternal);
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < m; i += kWindowThreads) symbols[w0 + i] = s_sym[i];
+}
+
+// Fallback for windows above the LDS limit (more than 2^30 pieces): a scatter
+// from the grouped pairs.
 __global__ void k_remap_scatter(const DigState *ds, const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
                                 const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
-                                int32_t *__restrict__ symbols) {
+                                int sh, int32_t *__restrict__ symbols) {
     const int64_t n = ds->n;
     const uint64_t *K = ctl[0] ? k1 : k0;
     const uint32_t *V = ctl[0] ? v1 : v0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-        symbols[K[q]] = (int32_t)V[q];
+        symbols[K[q] >> sh] = (int32_t)V[q];
 }
 
 // ------------------------------------------------------------ raw 2-D points
@@ -1671,15 +1735,28 @@ int remap(const DigWs &w, int64_t N, int32_t *symbols, hipStream_t st) {
     }
     int rc = radix_sort_init(w.sb, st);
     if (rc) return rc;
-    JB_LAUNCH(k_remap_pairs, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym,
+    // indices below 2^bits; the two sorted digits are the index's top 16 bits
+    // (the keys are shifted to end at bit 32), windows of 2^(bits - 16)
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < N) ++bits;
+    const int wlog = bits - 16;
+    const bool window = wlog <= kWindowMaxLog;
+    const int sh = window ? 32 - bits : 0;
+    JB_LAUNCH(k_remap_pairs, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, sh,
               w.sb.keys[0], w.sb.vals[0]);
     JB_LAUNCH_CHECK();
-    JB_LAUNCH(k_remap_hist, dim3(1), dim3(256), 0, st, w.ds, w.sb.ghist, w.sb.kmin);
+    JB_LAUNCH(k_remap_hist, dim3(1), dim3(256), 0, st, w.ds, sh, w.sb.ghist, w.sb.kmin);
     JB_LAUNCH_CHECK();
     rc = radix_sort_pairs(w.sb, &w.ds->n, N, st, "remap", /*keep_keys=*/true, /*sparse=*/false, /*prefix_digits=*/2);
     if (rc) return rc;
-    JB_LAUNCH(k_remap_scatter, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
-              w.sb.vals[1], w.sb.ctl, symbols);
+    if (window) {
+        const int64_t nwin = (N + ((int64_t)1 << wlog) - 1) >> wlog;
+        JB_LAUNCH(k_remap_window, dim3((unsigned)nwin), dim3(kWindowThreads), (size_t)4 << wlog, st, w.ds,
+                  w.sb.keys[0], w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, sh, wlog, symbols);
+    } else {
+        JB_LAUNCH(k_remap_scatter, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.sb.keys[0], w.sb.keys[1],
+                  w.sb.vals[0], w.sb.vals[1], w.sb.ctl, sh, symbols);
+    }
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
