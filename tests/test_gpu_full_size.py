@@ -1,7 +1,8 @@
 """Full-size parity for the uneven workload (50,000 series of log-uniform
 length, 7.2e8 points, 3.0e8 pieces) and the multivariate one (1,024 samples x
-64 channels of 5,000 points, 3.3e8 points), in the launch configuration the
-benchmark uses at these sizes: one Symbolizer on the default stream.
+64 channels of 5,000 points, 3.3e8 points): one Symbolizer on the default
+stream, and for the uneven workload also the benchmark's timed
+configuration (two buffer sets on their own streams, whole steps).
 
 Everything is compared with the oracle element by element over the whole
 workload: every piece (len, inc) and piece offset; sigma_len and sigma_inc;
@@ -79,6 +80,9 @@ class _FullSize:
         np.testing.assert_array_equal(opo, st["po"])
         np.testing.assert_array_equal(ol, st["ln"])
         np.testing.assert_array_equal(oi.view(np.uint64), st["inc"].view(np.uint64))
+        N = ol.size
+        idx = np.unique(np.concatenate([np.arange(0, N, 256), np.arange(min(1000, N)), np.arange(max(N - 1000, 0), N)]))
+        st["sample"] = (idx, ol[idx], oi[idx])  # pieces for the pipelined step's encode check
         del st["ln"], st["inc"]
         st["opo"] = opo
         st["dig"] = F.Digitization(ol, oi, w.alpha, w.scl, w.B)
@@ -170,11 +174,63 @@ class _FullSize:
         np.testing.assert_array_equal(g_cnt[: w.n_series], cnt)
         np.testing.assert_allclose(g_sse[: w.n_series], sse, rtol=1e-12, atol=1e-300)
         say(f"  reconstruct: all {out.size} points equal the oracle's; host RSS {_rss_gb():.1f} GB")
-        _state.clear()
+
+    pipelined_sets = 0
+
+    @pytest.mark.timeout(400)
+    def test_8_pipelined_step(self):
+        """The benchmark's timed configuration on this workload: buffer sets on
+        their own streams, two whole steps each (compress, encode against the
+        resident dictionary, digitize, reconstruct with the squared error).
+        Every set's symbols equal the oracle's; its encodings equal the
+        oracle's nearest centers on every 256th piece and both ends; its
+        reconstruction equals, bit for bit, the oracle's from the set's own
+        dictionary, whose lengths are the oracle's bit for bit."""
+        try:
+            if not self.pipelined_sets:
+                pytest.skip("the benchmark times one batch at a time on this workload")
+            st = self._s()
+            from paper_2401_00109_amd.pipeline import Pipeline
+            from paper_2401_00109_amd.serve import build_resident_dictionary
+            T = torch()
+            w, dig, opo = st["w"], st["dig"], st["opo"]
+            N = int(opo[-1])
+            t0h = np.where(np.diff(w.series_off) > 0,
+                           w.values[np.minimum(w.series_off[:-1], max(w.n_points - 1, 0))], 0.0)
+            v, so = to_dev(w.values), to_dev(w.series_off)
+            resident = build_resident_dictionary(DEV)
+            n_sets = self.pipelined_sets
+            say(f"  pipelined steps: {n_sets} sets, resident k={resident.size()}")
+            pipe = Pipeline(v, so, to_dev(t0h), w.D, w.tol, w.alpha, w.scl, w.B, N, resident, n_sets=n_sets,
+                            max_len=w.max_len)
+            pipe.run(2 * n_sets)
+            T.cuda.synchronize()
+            rd = resident.host()
+            idx, sl, si = st["sample"]
+            enc_exp = O.encode(sl, si, rd["sigma_len"], rd["sigma_inc"], rd["scl"], rd["cx"], rd["cy"])
+            for i, S in enumerate(pipe.sets):
+                assert S.steps == 2 and S.sz.status() == (0, 0)
+                np.testing.assert_array_equal(S.sz.symbols[:N].cpu().numpy(), dig.symbols)
+                np.testing.assert_array_equal(S.enc[:N].cpu().numpy()[idx], enc_exp)
+                d = S.sz.dictionary.host()
+                np.testing.assert_array_equal(d["center_len"].view(np.uint64), dig.center_len.view(np.uint64))
+                out, oo, sse, cnt = F.reconstruct(dig.symbols, opo, w.series_off, t0h, d["center_len"],
+                                                  d["center_inc"], w.values)
+                np.testing.assert_array_equal(S.rec.out_off.cpu().numpy(), oo)
+                np.testing.assert_array_equal(S.rec.out[: out.size].cpu().numpy().view(np.uint64),
+                                              out.view(np.uint64))
+                np.testing.assert_array_equal(S.rec.cnt[: w.n_series].cpu().numpy(), cnt)
+                np.testing.assert_allclose(S.rec.sse[: w.n_series].cpu().numpy(), sse, rtol=1e-12, atol=1e-300)
+                say(f"  set {i}: symbols, {idx.size} sampled encodings and {out.size} reconstructed points ok")
+            del pipe, v, so, resident
+            T.cuda.empty_cache()
+        finally:
+            _state.clear()
 
 
 class TestUneven(_FullSize):
     wid = 3
+    pipelined_sets = 2
 
 
 class TestMultivar(_FullSize):
