@@ -266,8 +266,8 @@ def measure(w, dev, resident, args, tuning, primary: bool) -> dict:
     S0 = sets[0]
     sz, full, enc, rec = S0.sz, S0.pieces, S0.enc, S0.rec
 
-    def run_steps(n, pipelined=True):
-        pipe.run(n, pipelined=pipelined)
+    def run_steps(n, pipelined=True, overlap=True):
+        pipe.run(n, pipelined=pipelined, overlap=overlap)
 
     run_steps(max(args.warmup, 1) * len(sets))
     torch.cuda.synchronize()
@@ -347,12 +347,13 @@ def measure(w, dev, resident, args, tuning, primary: bool) -> dict:
         f"{ms_graph if ms_graph is None else round(ms_graph, 3)} ms (tuning {graph_tuning})")
 
     # ---------------------------------------------------------------- per-kernel events
-    # The roofline is taken one batch at a time, so a kernel's duration is its
-    # own (with batches in flight a kernel shares the device with the other
-    # batch's kernels; those durations are reported beside it).
+    # The roofline is taken one batch at a time with each step's encoding on
+    # the step's own stream, so a kernel's duration is its own (with batches
+    # in flight a kernel shares the device with the other batch's kernels and
+    # the encodings; those durations are reported beside it).
     def kernel_times(pipelined):
         J.timing_enable(True)
-        run_steps(args.steps, pipelined=pipelined)
+        run_steps(args.steps, pipelined=pipelined, overlap=pipelined)
         torch.cuda.synchronize()
         rep = J.timing_report()
         J.timing_enable(False)

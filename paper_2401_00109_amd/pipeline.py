@@ -5,9 +5,12 @@ Each buffer set holds its own pieces, symbols, dictionary, encodings,
 reconstruction and scratch, and runs every step it is given on its own
 stream (default priority).  Consecutive steps go to consecutive sets, so one
 batch's compression (FP64-issue bound, a few wavefronts per compute unit)
-overlaps the other batches' sort, gathers and reconstruction.  Every step
-does all of its work; sets share only the read-only inputs and the resident
-dictionary.
+overlaps the other batches' sort, gathers and reconstruction.  Inside a
+step, the encoding needs only the compression's pieces, so it runs on a side
+stream shared by the sets while the set's own stream digitizes and
+reconstructs; the set's stream waits for it before its next step (whose
+compression rewrites the pieces).  Every step does all of its work; sets
+share only the read-only inputs and the resident dictionary.
 
 The sets are bound to one input batch held in device memory (values,
 series_off, t0), as in a throughput measurement or a replay of a resident
@@ -31,6 +34,8 @@ class BufferSet:
     rec: api.Reconstructor
     stream: torch.cuda.Stream
     encode_ws: torch.Tensor
+    compressed: torch.cuda.Event = field(default_factory=torch.cuda.Event)
+    encoded: torch.cuda.Event = field(default_factory=torch.cuda.Event)
     steps: int = field(default=0)
 
 
@@ -59,6 +64,7 @@ class Pipeline:
         n_points = values.numel()
         cap = max(n_points, 1)
         self.sets: list[BufferSet] = []
+        self.side = torch.cuda.Stream(device=dev)  # the sets' encodes
         capacity = self.max_pieces
         for i in range(n_sets):
             sz = api.Symbolizer(n_series, n_points, D, tol, alpha, scl, B, max_len=max_len,
@@ -78,29 +84,42 @@ class Pipeline:
             # sizes the other sets' dictionaries
             capacity = max(sz.dictionary.size(), 1)
 
-    def step(self, S: BufferSet):
-        """Enqueue one full step on set S's stream."""
+    def step(self, S: BufferSet, overlap: bool = True):
+        """Enqueue one full step on set S's stream (the encoding on the side
+        stream when overlap is True)."""
         st = S.stream
         S.sz.compress(self.values, self.series_off, stream=st)
+        est = st
+        if overlap:
+            S.compressed.record(st)
+            self.side.wait_event(S.compressed)
+            est = self.side
         api.encode(S.pieces.len, S.pieces.inc, S.pieces.n_pieces, self.max_pieces, self.resident, symbols=S.enc,
-                   workspace=S.encode_ws, stream=st)
+                   workspace=S.encode_ws, stream=est)
+        if overlap:
+            S.encoded.record(self.side)
         S.sz.digitize(stream=st)
         S.rec.run(S.sz.symbols, S.sz.dictionary, stream=st)
+        if overlap:
+            st.wait_event(S.encoded)
         S.steps += 1
 
-    def run(self, n_steps: int, pipelined: bool = True):
+    def run(self, n_steps: int, pipelined: bool = True, overlap: bool = True):
         """Enqueue n_steps steps: round robin over the sets, or all on the
-        first set when pipelined is False (one batch at a time).  The sets'
-        streams wait for the work already on the current stream, and the
-        current stream waits for the steps, so callers can time the call with
-        events on the current stream."""
+        first set when pipelined is False (one batch at a time); overlap
+        False keeps each step's encoding on its set's stream (every kernel
+        then runs on its own, for per-kernel timing).  The sets' streams and
+        the side stream wait for the work already on the current stream, and
+        the current stream waits for the steps, so callers can time the call
+        with events on the current stream."""
         cur = torch.cuda.current_stream()
         ev = torch.cuda.Event()
         ev.record(cur)
         for S in self.sets:
             S.stream.wait_event(ev)
+        self.side.wait_event(ev)
         for i in range(n_steps):
-            self.step(self.sets[i % len(self.sets)] if pipelined else self.sets[0])
+            self.step(self.sets[i % len(self.sets)] if pipelined else self.sets[0], overlap=overlap)
         for S in self.sets:
             e = torch.cuda.Event()
             e.record(S.stream)
