@@ -656,15 +656,17 @@ struct Active {
     int32_t *glist;
     int head, tail;
 
-    __device__ void push(int32_t pos, double kp, double xp, double yp) {
-        if (lane_id() == 0) {
-            const int sl = tail % kActCap;
+    // the lanes in `m`, in lane order, each with its own entry
+    __device__ void push_lanes(uint64_t m, int32_t pos, double kp, double xp, double yp) {
+        const int lane = lane_id();
+        if ((m >> lane) & 1ull) {
+            const int sl = (tail + __popcll(m & lanemask_lt())) % kActCap;
             c->k[sl] = kp;
             c->x[sl] = xp;
             c->y[sl] = yp;
             c->p[sl] = pos;
         }
-        ++tail;
+        tail += __popcll(m);
     }
     // entries [from, tail) to glist
     __device__ void flush(int from) {
@@ -728,7 +730,8 @@ __device__ __forceinline__ bool columns_separated(const DigState *ds, double scl
 // Points are staged kStage batches at a time (all loads of a chunk in flight
 // together); within a batch each lane first tests its point against the
 // active starts, oldest first, and the points no active start covers are
-// then resolved among themselves in lane order (one step per new start).
+// then resolved among themselves in lane order (runs of lanes separated by
+// key gaps above alpha side by side, one step per new start of a run).
 template <bool Col>
 __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__restrict__ key,
                            const double *__restrict__ x, const double *__restrict__ y, double alpha, double a2,
@@ -803,22 +806,38 @@ __device__ void pull_range(int64_t from, int64_t to, Active &A, const double *__
                         }
                     }
                 }
-                // the points no active start covers, resolved in lane order:
-                // the first becomes a start and covers later lanes, and so on
+                // The points no active start covers, resolved in lane order.
+                // A key more than alpha above the previous lane's starts a
+                // new run of lanes: keys ascend, so no point reaches across
+                // that gap, and the runs are resolved side by side.  At each
+                // step the first pending lane of every run becomes a start
+                // and covers the later lanes of its run; the batch's new
+                // starts then enter the list in position order.
                 uint64_t pend = ballot(open);
-                while (pend) {
-                    const int l = ffs64(pend);
-                    const double kl = readlane_f64(kq, l), xl = readlane_f64(xq, l), yl = readlane_f64(yq, l);
-                    const int32_t pl = (int32_t)(b0 + l);
-                    if (lane == l) {
-                        owner = pl;
-                        open = false;
-                    } else if (open && lane > l && covers_t<Col>(kq, xq, yq, kl, xl, yl, alpha, a2)) {
-                        owner = pl;
-                        open = false;
+                if (pend) {
+                    const double kprev = __shfl_up(kq, 1);
+                    const uint64_t heads = ballot(lane == 0 || !(kq - kprev <= alpha));
+                    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes [0, lane]
+                    const int rh = 63 - __builtin_clzll(heads & upto);               // this lane's run head
+                    const uint64_t run_before = lanemask_lt() & (~0ull << rh);       // lanes [rh, lane)
+                    uint64_t starts = 0ull;
+                    while (pend) {
+                        const bool first = open && (pend & run_before) == 0ull;
+                        starts |= ballot(first);
+                        // this lane's run's start of the step (a lane below it when
+                        // the lane is pending and not first)
+                        const int sl = ffs64(pend & (~0ull << rh));
+                        const double ks = __shfl(kq, sl), xs = __shfl(xq, sl), ys = __shfl(yq, sl);
+                        if (first) {
+                            owner = (int32_t)(b0 + lane);
+                            open = false;
+                        } else if (open && covers_t<Col>(kq, xq, yq, ks, xs, ys, alpha, a2)) {
+                            owner = (int32_t)(b0 + sl);
+                            open = false;
+                        }
+                        pend = ballot(open);
                     }
-                    A.push(pl, kl, xl, yl);
-                    pend = ballot(open);
+                    A.push_lanes(starts, (int32_t)(b0 + lane), kq, xq, yq);
                 }
             }
 #pragma unroll
