@@ -6,6 +6,7 @@
 #include <stddef.h>
 
 #include "jabba.h"
+#include "sort_plan.h"
 
 namespace jabba {
 
@@ -211,18 +212,21 @@ constexpr int kSortCtlMode = 40;
 // Global histograms of the eight digits of keys[0] (after the keys are written).
 int radix_global_hist(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st);
 // Sorts n (device count) pairs held in keys[0]/vals[0]; the result is in
-// keys[ctl[0]], vals[ctl[0]] (read on device by consumers).  With keep_keys
-// false only vals[ctl[0]] holds the result (the sorted order); the key
-// buffers then hold intermediate, narrowed keys.  sparse: the live count is
+// keys[ctl[0]], vals[ctl[0]] (read on device by consumers).  key_form
+// (sort_plan.h): kSortKeep64 keeps the 64-bit keys; kSortKeep32 takes and
+// keeps keys - kmin as 32-bit words (the key buffers read as uint32_t, every
+// key - kmin below 2^32); with kSortOrderOnly only vals[ctl[0]] holds the
+// result (the sorted order) and the key buffers hold intermediate, narrowed
+// keys.  sparse: the live count is
 // expected far below n_max (the passes then run persistent workgroups
 // instead of one per possible tile).
 // `tag` suffixes the timing names of the pass kernels ("" for the main sort).
 // prefix_digits > 0: only the highest prefix_digits digits below the top
 // non-constant one are sorted; the pairs leave grouped by
 // (key - kmin) >> ctl[kSortCtlPrefixShift], in input order within a group
-// (with keep_keys false, the values alone).
+// (with kSortOrderOnly, the values alone).
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st,
-                     const char *tag = "", bool keep_keys = true, bool sparse = false, int prefix_digits = 0);
+                     const char *tag = "", int key_form = kSortKeep64, bool sparse = false, int prefix_digits = 0);
 // ctl words a consumer of the sort reads: [0] the buffer holding the result,
 // [kSortCtlSkip + d] pass d skipped, [kSortCtlError] a look-back wait ran out,
 // [kSortCtlPrefixShift] the prefix shift of a prefix sort.

@@ -1220,15 +1220,16 @@ __global__ void k_remap(const DigState *ds, const uint32_t *__restrict__ perm, c
 }
 
 // The pairs' key is the canonical index shifted left by `sh` bits, so that
-// the two highest radix digits hold the index's highest 16 bits.
+// the two highest radix digits hold the index's highest 16 bits; the keys
+// are 32-bit words (the sort takes and keeps them at that width).
 __global__ void k_remap_pairs(const DigState *ds, const uint32_t *__restrict__ perm, const int32_t *__restrict__ lab,
                               const uint32_t *__restrict__ sidx, const int32_t *__restrict__ glab,
-                              const uint32_t *__restrict__ gsym, int sh, uint64_t *__restrict__ keys,
+                              const uint32_t *__restrict__ gsym, int sh, uint32_t *__restrict__ keys,
                               uint32_t *__restrict__ vals) {
     const int64_t n = ds->n;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t g = sidx[lab[p]];
-        keys[p] = (uint64_t)perm[p] << sh;
+        keys[p] = perm[p] << sh;
         vals[p] = gsym[glab[g]];
     }
 }
@@ -1272,8 +1273,8 @@ constexpr int kWindowMaxLog = 14;  // 16,384 symbols: 64 KB of LDS
 constexpr int kWindowThreads = 1024;
 constexpr int kWindowPer = (1 << kWindowMaxLog) / kWindowThreads;
 
-__global__ __launch_bounds__(kWindowThreads) void k_remap_window(DigState *ds, const uint64_t *__restrict__ k0,
-                                                                 const uint64_t *__restrict__ k1,
+__global__ __launch_bounds__(kWindowThreads) void k_remap_window(DigState *ds, const uint32_t *__restrict__ k0,
+                                                                 const uint32_t *__restrict__ k1,
                                                                  const uint32_t *__restrict__ v0,
                                                                  const uint32_t *__restrict__ v1, const int32_t *ctl,
                                                                  int sh, int wlog, int32_t *__restrict__ symbols) {
@@ -1282,14 +1283,14 @@ __global__ __launch_bounds__(kWindowThreads) void k_remap_window(DigState *ds, c
     const int64_t w0 = (int64_t)blockIdx.x << wlog;
     if (w0 >= n) return;
     const int m = (int)(n - w0 < ((int64_t)1 << wlog) ? n - w0 : ((int64_t)1 << wlog));
-    const uint64_t *K = ctl[0] ? k1 : k0;
+    const uint32_t *K = ctl[0] ? k1 : k0;
     const uint32_t *V = ctl[0] ? v1 : v0;
-    uint64_t kr[kWindowPer];
+    uint32_t kr[kWindowPer];
     uint32_t vr[kWindowPer];
 #pragma unroll
     for (int u = 0; u < kWindowPer; ++u) {
         const int i = u * kWindowThreads + (int)threadIdx.x;
-        kr[u] = i < m ? K[w0 + i] : 0ull;
+        kr[u] = i < m ? K[w0 + i] : 0u;
         vr[u] = i < m ? V[w0 + i] : 0u;
     }
     bool bad = false;
@@ -1311,11 +1312,11 @@ __global__ __launch_bounds__(kWindowThreads) void k_remap_window(DigState *ds, c
 
 // Fallback for windows above the LDS limit (more than 2^30 pieces): a scatter
 // from the grouped pairs.
-__global__ void k_remap_scatter(const DigState *ds, const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+__global__ void k_remap_scatter(const DigState *ds, const uint32_t *__restrict__ k0, const uint32_t *__restrict__ k1,
                                 const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1, const int32_t *ctl,
                                 int sh, int32_t *__restrict__ symbols) {
     const int64_t n = ds->n;
-    const uint64_t *K = ctl[0] ? k1 : k0;
+    const uint32_t *K = ctl[0] ? k1 : k0;
     const uint32_t *V = ctl[0] ? v1 : v0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
         symbols[K[q] >> sh] = (int32_t)V[q];
@@ -1734,7 +1735,7 @@ int bucket_sort(const DigWs &w, int64_t N, double scl, hipStream_t st) {
     JB_LAUNCH_CHECK();
     rc = radix_global_hist(w.sb2, w.n_large, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb2, w.n_large, N, st, "large", /*keep_keys=*/false, /*sparse=*/true);
+    rc = radix_sort_pairs(w.sb2, w.n_large, N, st, "large", kSortOrderOnly, /*sparse=*/true);
     if (rc) return rc;
     JB_LAUNCH_NAMED("k_large_emit", k_large_emit<Key>, dim3(grid_for(N, 4)), dim3(256), 0, st, w.sb.vals[0],
                     w.sb.vals[1], w.rec, w.sb.ctl, w.sb2.vals[0], w.sb2.vals[1], w.sb2.ctl, w.loff, w.tlarge, w.ds,
@@ -1762,18 +1763,20 @@ int remap(const DigWs &w, int64_t N, int32_t *symbols, hipStream_t st) {
     const bool window = wlog <= kWindowMaxLog;
     const int sh = window ? 32 - bits : 0;
     JB_LAUNCH(k_remap_pairs, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.perm, w.lab, w.sidx, w.glab, w.gsym, sh,
-              w.sb.keys[0], w.sb.vals[0]);
+              reinterpret_cast<uint32_t *>(w.sb.keys[0]), w.sb.vals[0]);
     JB_LAUNCH_CHECK();
     JB_LAUNCH(k_remap_hist, dim3(1), dim3(256), 0, st, w.ds, sh, w.sb.ghist, w.sb.kmin);
     JB_LAUNCH_CHECK();
-    rc = radix_sort_pairs(w.sb, &w.ds->n, N, st, "remap", /*keep_keys=*/true, /*sparse=*/false, /*prefix_digits=*/2);
+    rc = radix_sort_pairs(w.sb, &w.ds->n, N, st, "remap", kSortKeep32, /*sparse=*/false, /*prefix_digits=*/2);
     if (rc) return rc;
     if (window) {
         const int64_t nwin = (N + ((int64_t)1 << wlog) - 1) >> wlog;
         JB_LAUNCH(k_remap_window, dim3((unsigned)nwin), dim3(kWindowThreads), (size_t)4 << wlog, st, w.ds,
-                  w.sb.keys[0], w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, sh, wlog, symbols);
+                  reinterpret_cast<const uint32_t *>(w.sb.keys[0]), reinterpret_cast<const uint32_t *>(w.sb.keys[1]),
+                  w.sb.vals[0], w.sb.vals[1], w.sb.ctl, sh, wlog, symbols);
     } else {
-        JB_LAUNCH(k_remap_scatter, dim3(grid_for(N)), dim3(256), 0, st, w.ds, w.sb.keys[0], w.sb.keys[1],
+        JB_LAUNCH(k_remap_scatter, dim3(grid_for(N)), dim3(256), 0, st, w.ds,
+                  reinterpret_cast<const uint32_t *>(w.sb.keys[0]), reinterpret_cast<const uint32_t *>(w.sb.keys[1]),
                   w.sb.vals[0], w.sb.vals[1], w.sb.ctl, sh, symbols);
     }
     JB_LAUNCH_CHECK();
@@ -1848,7 +1851,7 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     // radix passes over the highest four varying digits (the order alone),
     // then every prefix group is put in (key, index) order and leaves as the
     // sorted arrays
-    rc = radix_sort_pairs(w.sb, n_live, N, st, "", /*keep_keys=*/false, /*sparse=*/false, kPrefixDigits);
+    rc = radix_sort_pairs(w.sb, n_live, N, st, "", kSortOrderOnly, /*sparse=*/false, kPrefixDigits);
     if (rc) return rc;
     rc = key_kind == kKeyPca ? bucket_sort<kKeyPca>(w, N, scl, st) : bucket_sort<kKeyNorm>(w, N, scl, st);
     if (rc) return rc;
@@ -1883,7 +1886,7 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     JB_LAUNCH_CHECK();
     rc = radix_global_hist(w.sb, w.g_count, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups", /*keep_keys=*/true, /*sparse=*/true);
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups", kSortKeep64, /*sparse=*/true);
     if (rc) return rc;
     JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
               w.sb.vals[1], w.sb.ctl, w.gk,
@@ -1982,7 +1985,7 @@ extern "C" int jabba_aggregate_points(const double *x, const double *y, const in
     JB_LAUNCH_CHECK();
     rc = radix_global_hist(w.sb, w.g_count, N, st);
     if (rc) return rc;
-    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups", /*keep_keys=*/true, /*sparse=*/true);
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "groups", kSortKeep64, /*sparse=*/true);
     if (rc) return rc;
     JB_LAUNCH(k_col_cuts, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.vals[0],
               w.sb.vals[1], w.sb.ctl, w.gk, w.gx, w.gy, alpha, w.cut, w.ord, w.ck, w.cx, w.cy);

@@ -164,7 +164,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
 // keys then leave grouped by (key - kmin) >> that shift, in input order
 // within a group (64 when no digit varies).
 __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ ghist, const int64_t *n_dev,
-                                                   int64_t n_max, int keep_keys, int prefix_digits, int32_t *ctl,
+                                                   int64_t n_max, int key_form, int prefix_digits, int32_t *ctl,
                                                    uint32_t *__restrict__ gbase) {
     __shared__ uint32_t s_wave[kThreads / kWave];
     __shared__ int s_full;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(const uint32_t *__restrict__ 
         for (int d = 7; d >= 0; --d)
             if (!skip[d]) first = d;
         ctl[kCtlFirst] = first;
-        ctl[kCtlBase] = sort_pass_modes(skip, keep_keys != 0, modes);
+        ctl[kCtlBase] = sort_pass_modes(skip, key_form, modes);
         for (int d = 0; d < 8; ++d) ctl[kCtlMode + d] = modes[d];
     }
 }
@@ -491,10 +491,10 @@ const char *pass_timer_name(const char *tag) {
 }  // namespace
 
 int radix_sort_pairs(const SortBuffers &b, const int64_t *n_dev, int64_t n_max, hipStream_t st, const char *tag,
-                     bool keep_keys, bool sparse, int prefix_digits) {
+                     int key_form, bool sparse, int prefix_digits) {
     const bool main_sort = !tag || !tag[0];
     const int64_t tiles = (n_max + kTileN - 1) / kTileN > 0 ? (n_max + kTileN - 1) / kTileN : 1;
-    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, keep_keys ? 1 : 0, prefix_digits, b.ctl,
+    JB_LAUNCH(k_plan, dim3(1), dim3(kThreads), 0, st, b.ghist, n_dev, n_max, key_form, prefix_digits, b.ctl,
               b.gbase);
     // A sparse sort's live count is far below its bound and known only on
     // the device: its passes run persistent workgroups, at most the resident

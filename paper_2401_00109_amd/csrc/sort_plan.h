@@ -7,7 +7,8 @@
 // above the highest active one can be dropped.  A sort whose caller needs
 // only the order carries 64-bit keys until the digits left to sort fit in 32
 // bits, then 32-bit keys (key - kmin shifted past the digits already sorted);
-// its last active pass writes the values alone.
+// its last active pass writes the values alone.  A sort whose keys minus kmin
+// are below 2^32 can carry them at 32 bits throughout and keep them.
 #pragma once
 
 #ifndef JB_HD
@@ -24,11 +25,21 @@ constexpr int kSortModeIn32 = 1;    // the pass reads 32-bit keys
 constexpr int kSortModeOut32 = 2;   // the pass writes 32-bit keys
 constexpr int kSortModeNoKeys = 4;  // the pass writes no keys (order only)
 
+// what the sort's caller gets besides the order
+constexpr int kSortOrderOnly = 0;  // nothing: keys narrow, the last pass writes values only
+constexpr int kSortKeep64 = 1;     // the sorted 64-bit keys
+constexpr int kSortKeep32 = 2;     // the sorted keys, stored as 32-bit key - kmin (< 2^32) from the start
+
 // skip[d] (d = 0..7): digit d of key - kmin is the same for every key.
-// Writes modes[d] (kSortMode* bits, 0 for skipped passes and when the keys
-// are kept) and returns the bit offset of the 32-bit keys inside key - kmin
+// Writes modes[d] (kSortMode* bits, 0 for skipped passes and 64-bit kept
+// keys) and returns the bit offset of the 32-bit keys inside key - kmin
 // (0 when no pass narrows).
-JB_HD inline int sort_pass_modes(const int *skip, bool keep_keys, int *modes) {
+JB_HD inline int sort_pass_modes(const int *skip, int key_form, int *modes) {
+    if (key_form == kSortKeep32) {
+        for (int d = 0; d < 8; ++d) modes[d] = skip[d] ? 0 : (kSortModeIn32 | kSortModeOut32);
+        return 0;
+    }
+    const bool keep_keys = key_form != kSortOrderOnly;
     int top = -1;
     for (int d = 0; d < 8; ++d)
         if (!skip[d]) top = d;

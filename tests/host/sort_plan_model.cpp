@@ -1,15 +1,16 @@
 // Host model of the radix sort's pass schedule: stable LSD passes of 8-bit
 // digits over key - kmin, skipping digits that are the same for every key,
 // moving the keys at the widths sort_pass_modes gives (64-bit, then 32-bit
-// keys shifted past the sorted digits, none after the last pass).  The order
-// must be the stable order of the keys.
+// keys shifted past the sorted digits, none after the last pass; or 32-bit
+// key - kmin from the start for the kept 32-bit form).  The order must be the
+// stable order of the keys, and kept keys must leave sorted.
 #include <stdint.h>
 
 #include <vector>
 
 #include "sort_plan.h"
 
-extern "C" int plan_sort(const uint64_t *keys, int64_t n, int keep_keys, uint32_t *order, int *modes_out,
+extern "C" int plan_sort(const uint64_t *keys, int64_t n, int key_form, uint32_t *order, int *modes_out,
                          int *base_out, int64_t *bytes_out) {
     uint64_t kmin = ~0ull;
     for (int64_t i = 0; i < n; ++i) kmin = keys[i] < kmin ? keys[i] : kmin;
@@ -24,12 +25,20 @@ extern "C" int plan_sort(const uint64_t *keys, int64_t n, int keep_keys, uint32_
                 break;
             }
     }
-    const int base = jabba::sort_pass_modes(skip, keep_keys != 0, modes_out);
+    const int base = jabba::sort_pass_modes(skip, key_form, modes_out);
     *base_out = base;
     std::vector<uint64_t> k64(keys, keys + n), t64(n);
     std::vector<uint32_t> k32(n), t32(n), v(n), tv(n);
     for (int64_t i = 0; i < n; ++i) v[i] = (uint32_t)i;
     bool have64 = true, have32 = false;
+    if (key_form == jabba::kSortKeep32) {  // the caller writes key - kmin as 32-bit words
+        for (int64_t i = 0; i < n; ++i) {
+            if (keys[i] - kmin > 0xFFFFFFFFull) return -2;
+            k32[i] = (uint32_t)(keys[i] - kmin);
+        }
+        have64 = false;
+        have32 = true;
+    }
     int64_t bytes = 0;
     for (int d = 0; d < 8; ++d) {
         if (skip[d]) continue;
@@ -64,5 +73,10 @@ extern "C" int plan_sort(const uint64_t *keys, int64_t n, int keep_keys, uint32_
     }
     for (int64_t i = 0; i < n; ++i) order[i] = v[i];
     *bytes_out = bytes;
+    if (key_form == jabba::kSortKeep32) {  // the kept keys must leave in sorted order
+        if (!have32) return -3;
+        for (int64_t i = 0; i < n; ++i)
+            if ((uint64_t)k32[i] + kmin != keys[v[i]]) return -4;
+    }
     return 0;
 }
