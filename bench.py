@@ -177,6 +177,8 @@ def main() -> int:
         del w2
 
     serving = None if args.no_serving else serving_leg(resident, dev, args)
+    copy = copy_ceiling(dev)
+    log(f"copy ceiling: {copy['achieved']:.0f} GB/s ({100 * copy['frac']:.1f} % of {HBM_PEAK_GBS:.0f})")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -207,6 +209,7 @@ def main() -> int:
                    "batches_in_flight": head["n_sets"]},
         "path_roofline": head["path_roofline"],
         "roofline": head["roofline"],
+        "copy_ceiling": copy,
         "dominant_kernel_with_batches_in_flight": head["in_flight"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "symbolize_points_per_s": head["symbolize_points_per_s"],
@@ -538,6 +541,31 @@ def serving_leg(resident, dev, args) -> dict:
             "requests_shape": "1-256 random walks of 500-50,000 points (log-uniform), cycling over "
                               f"{len(pool)} distinct request bodies; four slots; 200 warm-up requests",
             "latency": "arrival to symbols on the host, H2D and D2H included"}
+
+
+def copy_ceiling(dev, gib: int = 2, reps: int = 10) -> dict:
+    """What a plain device copy reaches on this GPU: torch's copy kernel over
+    `gib` GiB of float64 (that much read and written per launch), timed with
+    events over `reps` launches after a warm-up."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2.0 * n * 8
+    del a, b
+    torch.cuda.empty_cache()
+    gbs = moved / (ms / 1e3) / 1e9
+    return {"kernel": f"torch copy_ of {gib} GiB float64", "bytes_per_launch": moved, "avg_launch_ms": round(ms, 4),
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def _traffic(kernel: str, workload: str):

@@ -26,6 +26,7 @@ import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CAL_BYTES = float(1 << 30)
+PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def _code_only(text: str) -> str:
@@ -166,20 +167,36 @@ def main() -> int:
                    "kernels": traffic}, fh, indent=1, sort_keys=True)
 
     stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    # counted HBM bytes over kernel time, per kernel and weighted by time over
+    # every kernel of the library that has both figures
+    tot_bytes = tot_ns = 0.0
+    for r in stats:
+        t = traffic.get(timing_name(r["Name"]), {})
+        if "jabba" in r["Name"] and t.get("bytes_per_launch") is not None:
+            tot_bytes += t["bytes_per_launch"] * float(r["Calls"])
+            tot_ns += float(r["TotalDurationNs"])
+    weighted = (f"Time-weighted over the library's kernels: {tot_bytes / tot_ns:.0f} GB/s of counted traffic, "
+                f"{100 * tot_bytes / tot_ns / PEAK_GBS:.1f} % of {PEAK_GBS:.0f} GB/s" if tot_ns > 0 else
+                "Time-weighted counted traffic: not available")
     lines = [f"# Kernel time and HBM traffic, workload `{args.workload}`", "",
              f"Command: `{args.command}`", "",
              f"Source hash of the kernels: `{source_hash()}`", "",
              f"Counter scaling from the 1 GiB copy kernel: FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {wf:.4f}"
              if ff and wf else "Counter scaling: calibration kernel missing", "",
-             "| kernel | calls | total ms | avg us | % | fetch MB/launch | write MB/launch |",
-             "|---|---|---|---|---|---|---|"]
+             weighted, "",
+             "| kernel | calls | total ms | avg us | % | fetch MB/launch | write MB/launch | counted GB/s | % of peak |",
+             "|---|---|---|---|---|---|---|---|---|"]
     for r in stats[:24]:
         tn = timing_name(r["Name"])
         t = traffic.get(tn, {})
         fb, wb = t.get("fetch_bytes_per_launch"), t.get("write_bytes_per_launch")
+        bl = t.get("bytes_per_launch")
+        avg_ns = float(r["AverageNs"])
+        gbs = bl / avg_ns if (bl is not None and avg_ns > 0) else None
         lines.append(f"| {tn} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
-                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} | "
-                     f"{'' if fb is None else f'{fb / 1e6:.1f}'} | {'' if wb is None else f'{wb / 1e6:.1f}'} |")
+                     f"{avg_ns / 1e3:.2f} | {float(r['Percentage']):.1f} | "
+                     f"{'' if fb is None else f'{fb / 1e6:.1f}'} | {'' if wb is None else f'{wb / 1e6:.1f}'} | "
+                     f"{'' if gbs is None else f'{gbs:.0f}'} | {'' if gbs is None else f'{100 * gbs / PEAK_GBS:.1f}'} |")
     path = os.path.join(args.out, f"kernels_{args.workload}.md")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
