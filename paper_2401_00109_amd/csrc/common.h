@@ -122,6 +122,12 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src); }
 __device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) { return __shfl(v, src); }
 __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src); }

@@ -1156,6 +1156,102 @@ __global__ __launch_bounds__(256) void k_group_sums(const int64_t *__restrict__ 
     }
 }
 
+// Stage II sums: the Stage I sums of every starting point added to its
+// global owner.  The pairs (owner, starting point) are sorted by owner
+// (stably, so each owner's members stay in position order), which makes each
+// owner's members contiguous, and one wavefront per global start then adds
+// only its own members, where a scan of the start's key window in position
+// order reads every starting point of the window.  The increments are added
+// as that scan adds them: a member q of start g sits at lane (q - g) mod 64 of
+// chunk (q - g) / 64, each chunk is summed by the pairwise wavefront tree and
+// the chunks are added in order (a chunk without members adds +0 there and
+// is skipped here).
+__global__ void k_owner_pairs(const int64_t *__restrict__ g_count, const int32_t *__restrict__ glab,
+                              uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t G = *g_count;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+        keys[g] = (uint64_t)(uint32_t)glab[g];
+        vals[g] = (uint32_t)g;
+    }
+}
+
+// first position of each owner's members in the sorted pairs
+__global__ void k_owner_heads(const int64_t *__restrict__ g_count, const uint64_t *__restrict__ k0,
+                              const uint64_t *__restrict__ k1, const int32_t *__restrict__ ctl,
+                              uint32_t *__restrict__ head) {
+    const int64_t G = *g_count;
+    const uint64_t *K = ctl[0] ? k1 : k0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x)
+        if (i == 0 || K[i] != K[i - 1]) head[K[i]] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_owner_sums(const int64_t *__restrict__ g_count,
+                                                    const uint32_t *__restrict__ gflag,
+                                                    const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+                                                    const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
+                                                    const int32_t *__restrict__ ctl, const uint32_t *__restrict__ head,
+                                                    const int64_t *__restrict__ wcnt, const int64_t *__restrict__ wlen,
+                                                    const double *__restrict__ winc, int64_t *__restrict__ ocnt,
+                                                    int64_t *__restrict__ olen, double *__restrict__ oinc) {
+    const int lane = lane_id();
+    const int64_t G = *g_count;
+    const uint64_t *K = ctl[0] ? k1 : k0;
+    const uint32_t *V = ctl[0] ? v1 : v0;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < G; g += waves) {
+        if (!gflag[g]) continue;
+        int64_t c = 0, l = 0;
+        double ic = 0.0, chunk = 0.0;
+        int64_t cur = -1;  // chunk being gathered in `chunk`
+        for (int64_t i0 = head[g];; i0 += kWave) {
+            const int64_t i = i0 + lane;
+            const bool mem = i < G && K[i] == (uint64_t)g;
+            const uint64_t mm = ballot(mem);
+            int64_t cq = 0, lq = 0;
+            double iq = 0.0;
+            int64_t d = 0;  // the member's offset from its start
+            if (mem) {
+                const uint32_t q = V[i];
+                cq = wcnt[q];
+                lq = wlen[q];
+                iq = winc[q];
+                d = (int64_t)q - g;
+            }
+            c += wave_sum_i64(cq);
+            l += wave_sum_i64(lq);
+            // members ascend in position, so their chunks ascend in lane order
+            uint64_t todo = mm;
+            while (todo) {
+                const int64_t ch = readlane_i64(d >> 6, ffs64(todo));
+                if (ch != cur) {
+                    if (cur >= 0) ic = ic + wave_tree_sum(chunk);
+                    chunk = 0.0;
+                    cur = ch;
+                }
+                const bool here = ((todo >> lane) & 1ull) && (d >> 6) == ch;
+                const uint64_t hm = ballot(here);
+                // lane t takes the member whose offset is t within the chunk
+                uint64_t src = hm;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    const uint64_t bb = ballot(here && ((d >> b) & 1));
+                    src &= ((lane >> b) & 1) ? bb : ~bb;
+                }
+                const double v = __shfl(iq, src ? __builtin_ctzll(src) : 0);
+                if (src) chunk = chunk + v;
+                todo &= ~hm;
+            }
+            if (mm != ~0ull) break;  // the owner's members end in this batch
+        }
+        if (cur >= 0) ic = ic + wave_tree_sum(chunk);
+        if (lane == 0) {
+            ocnt[g] = c;
+            olen[g] = l;
+            oinc[g] = ic;
+        }
+    }
+}
+
 __global__ void k_compact_starts(const DigState *ds, const uint32_t *__restrict__ flag,
                                  const uint32_t *__restrict__ sidx, const double *__restrict__ sk,
                                  const double *__restrict__ sx, const double *__restrict__ sy,
@@ -1902,10 +1998,21 @@ int digitize_impl(const int32_t *len, const double *inc, const int64_t *n_pieces
     JB_LAUNCH_CHECK();
     rc = scan_u32_to_u32(w.gflag, w.gsym, w.g_count, N, w.scan_ws, st);
     if (rc) return rc;
-    JB_LAUNCH((k_group_sums<false>), dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, N, w.g_count,
-              (const int32_t *)nullptr, (const int32_t *)nullptr, (const int64_t *)nullptr, (const uint32_t *)nullptr,
-              w.gflag, w.gk, w.glab, (const int32_t *)nullptr, w.gcnt, w.glen, w.ginc,
-              alpha, w.ocnt, w.olen, w.oinc);
+    // Stage II sums by owner (the column sort's buffers are free again)
+    rc = radix_sort_init(w.sb, st);
+    if (rc) return rc;
+    JB_LAUNCH(k_owner_pairs, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.glab, w.sb.keys[0], w.sb.vals[0]);
+    JB_LAUNCH_CHECK();
+    rc = radix_global_hist(w.sb, w.g_count, N, st);
+    if (rc) return rc;
+    rc = radix_sort_pairs(w.sb, w.g_count, N, st, "owners", kSortKeep64, /*sparse=*/true);
+    if (rc) return rc;
+    JB_LAUNCH(k_owner_heads, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.sb.keys[0], w.sb.keys[1], w.sb.ctl,
+              w.cgid);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_owner_sums, dim3(grid_for(N * kWave, 16)), dim3(256), 0, st, w.g_count, w.gflag, w.sb.keys[0],
+              w.sb.keys[1], w.sb.vals[0], w.sb.vals[1], w.sb.ctl, w.cgid, w.gcnt, w.glen, w.ginc, w.ocnt, w.olen,
+              w.oinc);
     JB_LAUNCH_CHECK();
     JB_LAUNCH(k_dict, dim3(grid_for(N)), dim3(256), 0, st, w.g_count, w.gflag, w.gsym, w.ocnt, w.olen, w.oinc, w.ds,
               scl, *dict);

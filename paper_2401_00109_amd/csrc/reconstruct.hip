@@ -63,11 +63,6 @@ __device__ __forceinline__ int64_t wave_shr1_i64(int64_t v, int64_t first) {
 }
 
 // value of lane l, l uniform across the wavefront (scalar reads, no LDS)
-__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 __device__ __forceinline__ u128 readlane_u128(u128 v, int l) {
     const uint64_t lo = (uint64_t)readlane_i64((int64_t)(uint64_t)v, l);
     const uint64_t hi = (uint64_t)readlane_i64((int64_t)(uint64_t)(v >> 64), l);
