@@ -583,10 +583,12 @@ __global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t
     // round; a refill at the start of each iteration with rr % kQ1 == 0
     // stores pre[] at [le, le + kQ1).  A domain started at iteration rr0 reads
     // q0 = s + 3 first and meets its first refill k = (kQ1 - rr0 % kQ1) % kQ1
-    // rounds later; staging [q0, q0 + k + kQ1) keeps every q it reads inside
-    // [le - kR1, le) from then on (right after a refill le - q = kR1, just
-    // before one le - q = kQ1 + 1), and a refill overwrites only points below
-    // the next q.
+    // rounds later, when it reads q1 = q0 + k.  Staging [s + 1, L) with any L
+    // in [q1, q1 + kQ1] keeps every q it reads inside [le - kR1, le) from then on
+    // (right after a refill kQ1 <= le - q <= kR1, just before one
+    // 1 <= le - q <= kQ1 + 1), and a refill overwrites only points below the
+    // next q.  L is taken as a multiple of kQ1, so that every refill loads
+    // kQ1 points of one aligned 128-byte line.
     auto start_domain = [&](int32_t d) {
         dom = d;
         const Dom x = doms[dom];
@@ -607,8 +609,10 @@ __global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t
         S1c = 0.0;
         const int k = (int)((kQ1 - (rr & (kQ1 - 1))) & (kQ1 - 1));
         const int64_t q0 = s + 3;
-        le = q0 + k + kQ1;
-        for (int64_t p = q0; p < le; ++p) ring[p & (kR1 - 1)] = value(p <= e ? p : e);
+        le = (q0 + k + kQ1 - 1) & ~(int64_t)(kQ1 - 1);
+        // from s + 1: the exact evaluation reads points s + 1 .. q - 2 through
+        // the ring wherever they lie in its window (le - (s + 1) <= kR1)
+        for (int64_t p = s + 1; p < le; ++p) ring[p & (kR1 - 1)] = value(p <= e ? p : e);
         load_pre();
     };
 

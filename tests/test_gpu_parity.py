@@ -155,6 +155,26 @@ def test_compress_edge_cases(case):
         np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
 
 
+def test_compress_exact_path_in_later_domains():
+    # tol = 0 on straight lines leaves the certified filter undecided at every
+    # candidate, so each round evaluates the definition itself, reading the
+    # piece's points back (from the lane's ring where they lie in its
+    # window).  With many more domains than lanes, lanes take new domains
+    # from the queue between refills; their first rounds must read the new
+    # domain's points, not what the ring held for the domain before.
+    vals, off = pack([3.0 + 0.25 * np.arange(100_000) for _ in range(40)])
+    D, tol = 8, 0.0
+    say(f"compress, exact path in {40 * 100_000 // D} short domains")
+    ln, inc, po, st = gpu_compress(vals, off, D, tol)
+    assert st == 0
+    ol, oi, opo = O.compress(vals, off, D, tol)
+    np.testing.assert_array_equal(po, opo)
+    np.testing.assert_array_equal(ln, ol)
+    np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+    # every domain is one piece: 12,499 of 8 intervals and one of 7 per series
+    assert ol.size == 40 * 12_500 and np.count_nonzero(ol == 7) == 40 and np.count_nonzero(ol == 8) == 40 * 12_499
+
+
 def test_compress_empty_input():
     say("compress empty input")
     ln, inc, po, st = gpu_compress(np.zeros(0), np.zeros(1, np.int64), 10, 0.1)
