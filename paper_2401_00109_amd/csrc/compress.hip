@@ -530,7 +530,7 @@ constexpr int kQ1 = kR1 / 2;      // points per refill, and rounds between refil
 
 size_t compress1_lds_per_wave() { return (size_t)kWave * (kR1 + 1) * sizeof(double); }
 
-template <bool Norm>
+template <bool Norm, bool Grouped>
 __global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t, const Dom *__restrict__ doms,
                                                     const int32_t *__restrict__ queue,
                                                     const int64_t *__restrict__ n_dom_p, int32_t *__restrict__ q_head,
@@ -561,6 +561,17 @@ __global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t
     double zm = 0.0, zs = 1.0;
     double pre[kQ1];    // points [le, le + kQ1), stored at the next refill
     uint32_t rr = 0;    // iteration count, the same on every lane
+    // Grouped: pieces are kept in groups of four staging slots aligned to the
+    // slot index and leave as one 16-byte store of lengths and two of
+    // increments when a group is complete; a domain's first and last groups,
+    // which share their slots with its neighbours, leave slot by slot.  That
+    // takes the piece stores from two to three-quarters of an instruction per
+    // piece, which pays when there are at least as many domains as lanes (the
+    // vector-memory pipeline bounds the kernel then); with fewer domains the
+    // per-round latency does, and each piece is stored at once.
+    int32_t gl0 = 0, gl1 = 0, gl2 = 0, gl3 = 0;
+    double gi0 = 0.0, gi1 = 0.0, gi2 = 0.0, gi3 = 0.0;
+    int gfirst = 0;     // first slot of the current group that is this domain's
 
     auto value = [&](int64_t p) -> double {
         if constexpr (Norm) {
@@ -596,6 +607,7 @@ __global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t
         e = x.start + x.nint;
         obase = x.start;
         np = 0;
+        gfirst = (int)(obase & 3);
         if constexpr (Norm) {
             zm = zmean[x.series];
             zs = zstd[x.series];
@@ -677,15 +689,55 @@ __global__ __launch_bounds__(1024) void k_compress1(const double *__restrict__ t
             // the piece ends at the last accepted length, on point s + c - 1
             const int32_t L = c - 1;
             if (!isfinite(tpk)) set_status(status, kStNonFinite);
-            st_len[obase + np] = L;
-            st_inc[obase + np] = tpk - ts;
+            const int64_t idx = obase + np;
+            const int slot = (int)(idx & 3);
+            const double iv = tpk - ts;
+            if constexpr (!Grouped) {
+                st_len[idx] = L;
+                st_inc[idx] = iv;
+            }
+            gl0 = slot == 0 ? L : gl0;
+            gl1 = slot == 1 ? L : gl1;
+            gl2 = slot == 2 ? L : gl2;
+            gl3 = slot == 3 ? L : gl3;
+            gi0 = slot == 0 ? iv : gi0;
+            gi1 = slot == 1 ? iv : gi1;
+            gi2 = slot == 2 ? iv : gi2;
+            gi3 = slot == 3 ? iv : gi3;
             ++np;
             s += L;
             ts = tpk;
             c = 2;
             S2c = 0.0;
             S1c = 0.0;
-            if (s >= e) {
+            const bool last = s >= e;
+            if (Grouped && (slot == 3 || last)) {
+                const int64_t g0 = idx - slot;
+                if (gfirst == 0 && slot == 3) {
+                    *reinterpret_cast<int4 *>(st_len + g0) = make_int4(gl0, gl1, gl2, gl3);
+                    *reinterpret_cast<double2 *>(st_inc + g0) = make_double2(gi0, gi1);
+                    *reinterpret_cast<double2 *>(st_inc + g0 + 2) = make_double2(gi2, gi3);
+                } else {
+                    if (gfirst <= 0 && slot >= 0) {
+                        st_len[g0] = gl0;
+                        st_inc[g0] = gi0;
+                    }
+                    if (gfirst <= 1 && slot >= 1) {
+                        st_len[g0 + 1] = gl1;
+                        st_inc[g0 + 1] = gi1;
+                    }
+                    if (gfirst <= 2 && slot >= 2) {
+                        st_len[g0 + 2] = gl2;
+                        st_inc[g0 + 2] = gi2;
+                    }
+                    if (gfirst <= 3 && slot >= 3) {
+                        st_len[g0 + 3] = gl3;
+                        st_inc[g0 + 3] = gi3;
+                    }
+                }
+                gfirst = 0;
+            }
+            if (last) {
                 dom_count[dom] = np;
                 dom = -1;
             }
@@ -893,18 +945,33 @@ int finish(const CompressWs &w, int64_t n_series, int64_t total_points, int32_t 
     return JABBA_OK;
 }
 
+// units: the host's upper bound on the work units (domains or segments)
 template <int W>
 void launch_w(dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
-              int64_t dbase, int64_t dend, double tol2, int32_t max_len, const double *zmean, const double *zstd) {
+              int64_t dbase, int64_t dend, double tol2, int32_t max_len, const double *zmean, const double *zstd,
+              int64_t units) {
     if constexpr (W == 1) {
         const size_t lds = compress1_lds_per_wave() * (b.x / kWave);
-        if (zmean)
-            JB_LAUNCH_NAMED("k_compress_znorm", k_compress1<true>, g, b, lds, st, t, w.doms, w.queue, n_dom_p,
-                            w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean,
-                            zstd);
-        else
-            JB_LAUNCH_NAMED("k_compress<W>", k_compress1<false>, g, b, lds, st, t, w.doms, w.queue, n_dom_p, w.q_head,
-                            dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count, w.status, zmean, zstd);
+        const bool grouped = units >= (int64_t)g.x * b.x;  // at least one unit per lane
+        if (zmean) {
+            if (grouped)
+                JB_LAUNCH_NAMED("k_compress_znorm", (k_compress1<true, true>), g, b, lds, st, t, w.doms, w.queue,
+                                n_dom_p, w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count,
+                                w.status, zmean, zstd);
+            else
+                JB_LAUNCH_NAMED("k_compress_znorm", (k_compress1<true, false>), g, b, lds, st, t, w.doms, w.queue,
+                                n_dom_p, w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count,
+                                w.status, zmean, zstd);
+        } else {
+            if (grouped)
+                JB_LAUNCH_NAMED("k_compress<W>", (k_compress1<false, true>), g, b, lds, st, t, w.doms, w.queue,
+                                n_dom_p, w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count,
+                                w.status, zmean, zstd);
+            else
+                JB_LAUNCH_NAMED("k_compress<W>", (k_compress1<false, false>), g, b, lds, st, t, w.doms, w.queue,
+                                n_dom_p, w.q_head, dbase, dend, tol2, max_len, w.st_len, w.st_inc, w.dom_count,
+                                w.status, zmean, zstd);
+        }
     } else {
         const size_t lds = compress_lds_per_wave<W>() * (b.x / kWave);
         if (zmean)
@@ -936,14 +1003,16 @@ int launch_repair(const CompressWs &w, const int64_t *n_dom_p, int64_t n_series,
     return JABBA_OK;
 }
 
+// units: an upper bound on the work units the launch takes (domains or
+// segments), which picks between forms of the one-lane kernel
 int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
                     const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len,
-                    const double *zmean, const double *zstd);
+                    const double *zmean, const double *zstd, int64_t units);
 
 // segments: one group per work unit, assigned statically (segments are of
 // nearly equal length, so no queue is needed)
 int launch_segments(int W, int wpb, hipStream_t st, const double *t, const CompressWs &w, const int64_t *n_dom_p,
-                    int64_t n_series, int64_t total_points, int32_t D, double tol2, int32_t max_len,
+                    int64_t n_series, int64_t total_points, int32_t D, int32_t G, double tol2, int32_t max_len,
                     const double *zmean, const double *zstd) {
     const int64_t md = max_domains(n_series, total_points, D);
     const int64_t groups_per_block = (int64_t)wpb * (kWave / W);
@@ -951,7 +1020,7 @@ int launch_segments(int W, int wpb, hipStream_t st, const double *t, const Compr
     if (blocks < 1) blocks = 1;
     if (blocks > ((int64_t)1 << 31) - 1) return JABBA_EOVERFLOW;
     return launch_compress(W, dim3((unsigned)blocks), dim3((unsigned)(wpb * kWave)), st, t, w, n_dom_p, 0, md, tol2,
-                           max_len, zmean, zstd);
+                           max_len, zmean, zstd, total_points / G + total_points / D + n_series);
 }
 
 // Segment length from the tuning: negative = whole domains; 0 = the default,
@@ -991,15 +1060,15 @@ size_t lds_per_wave(int W) {
 
 int launch_compress(int W, dim3 g, dim3 b, hipStream_t st, const double *t, const CompressWs &w,
                     const int64_t *n_dom_p, int64_t dbase, int64_t dend, double tol2, int32_t max_len,
-                    const double *zmean, const double *zstd) {
+                    const double *zmean, const double *zstd, int64_t units) {
     switch (W) {
-        case 1: launch_w<1>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
-        case 2: launch_w<2>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
-        case 4: launch_w<4>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
-        case 8: launch_w<8>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
-        case 16: launch_w<16>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
-        case 32: launch_w<32>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
-        case 64: launch_w<64>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd); break;
+        case 1: launch_w<1>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
+        case 2: launch_w<2>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
+        case 4: launch_w<4>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
+        case 8: launch_w<8>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
+        case 16: launch_w<16>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
+        case 32: launch_w<32>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
+        case 64: launch_w<64>(g, b, st, t, w, n_dom_p, dbase, dend, tol2, max_len, zmean, zstd, units); break;
         default: return JABBA_EINVAL;
     }
     JB_LAUNCH_CHECK();
@@ -1053,10 +1122,11 @@ extern "C" int jabba_compress(const double *values, const int64_t *series_off, i
     rc = domain_table(w, series_off, n_series, total_points, D, G, G >= D, st);
     if (rc) return rc;
     const int64_t *n_dom_p = w.dom_off + n_series;
-    rc = G < D ? launch_segments(W, wpb, st, values, w, n_dom_p, n_series, total_points, D, tol * tol, max_len,
+    rc = G < D ? launch_segments(W, wpb, st, values, w, n_dom_p, n_series, total_points, D, G, tol * tol, max_len,
                                  nullptr, nullptr)
                : launch_compress(W, dim3((unsigned)(device_cu_count() * bpc)), dim3((unsigned)(wpb * kWave)), st,
-                                 values, w, n_dom_p, -1, 0, tol * tol, max_len, nullptr, nullptr);
+                                 values, w, n_dom_p, -1, 0, tol * tol, max_len, nullptr, nullptr,
+                                 total_points / D + n_series);
     if (rc) return rc;
     if (G < D) {
         rc = launch_repair(w, n_dom_p, n_series, total_points, D, values, tol * tol, max_len, nullptr, nullptr, st);
@@ -1103,10 +1173,11 @@ extern "C" int jabba_compress_znorm(const double *values, const int64_t *series_
     }
     const int64_t *n_dom_p = w.dom_off + n_series;
     const double *zm = n_series > 0 ? mean : nullptr;
-    rc = G < D ? launch_segments(W, wpb, st, values, w, n_dom_p, n_series, total_points, D, tol * tol, max_len, zm,
+    rc = G < D ? launch_segments(W, wpb, st, values, w, n_dom_p, n_series, total_points, D, G, tol * tol, max_len, zm,
                                  std_dev)
                : launch_compress(W, dim3((unsigned)(device_cu_count() * bpc)), dim3((unsigned)(wpb * kWave)), st,
-                                 values, w, n_dom_p, -1, 0, tol * tol, max_len, zm, std_dev);
+                                 values, w, n_dom_p, -1, 0, tol * tol, max_len, zm, std_dev,
+                                 total_points / D + n_series);
     if (rc) return rc;
     if (G < D && n_series > 0) {
         rc = launch_repair(w, n_dom_p, n_series, total_points, D, values, tol * tol, max_len, mean, std_dev, st);
@@ -1137,7 +1208,7 @@ extern "C" int jabba_compress_plain(const double *values, const int64_t *series_
         const int64_t nd = n >= 2 ? (n - 1 + D - 1) / D : 0;
         if (nd > 0) {
             rc = launch_compress(64, dim3((unsigned)nd), dim3(kWave), st, values, w, n_dom_p, d0, d0 + nd,
-                                 tol * tol, max_len, nullptr, nullptr);
+                                 tol * tol, max_len, nullptr, nullptr, nd);
             if (rc) return rc;
         }
         d0 += nd;
