@@ -6,7 +6,10 @@
 //    halves away from zero.  Every center length >= 1 is an integer multiple
 //    of 2^-52, so the running sums are exact unsigned 128-bit integers at
 //    scale 2^52: a wavefront inclusive scan plus a carry from the previous
-//    chunk, then S_j = (C_j + 2^51) >> 52 and len^_j = S_j - S_{j-1}.
+//    chunk, then S_j = (C_j + 2^51) >> 52 and len^_j = S_j - S_{j-1}.  When
+//    every center length of a chunk is below 2^25 the scan runs on three
+//    32-bit limbs (integer part, two 26-bit halves of the fraction), whose
+//    64-lane sums cannot overflow.
 //  * Values: V_j = V_{j-1} + inc~_j is a sequential binary64 recurrence; the
 //    wavefront walks it one lane per step (a DPP shift and one addition), so
 //    every V_j has the bits of the plain left-to-right evaluation.
@@ -44,6 +47,17 @@ __device__ __forceinline__ u128 wave_incl_scan_u128(u128 x) {
     x += dpp_u128<0x118, 0xf>(x);
     x += dpp_u128<0x142, 0xa>(x);
     x += dpp_u128<0x143, 0xc>(x);
+    return x;
+}
+
+// inclusive scan of a u32 across the 64 lanes, the same steps as above
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += dpp_u32<0x111, 0xf>(x);
+    x += dpp_u32<0x112, 0xf>(x);
+    x += dpp_u32<0x114, 0xf>(x);
+    x += dpp_u32<0x118, 0xf>(x);
+    x += dpp_u32<0x142, 0xa>(x);
+    x += dpp_u32<0x143, 0xc>(x);
     return x;
 }
 
@@ -252,7 +266,7 @@ constexpr int kFillThreads = kReconThreads - kWave;
 // sums its own points in order, and the 64 partials are added by one fixed
 // tree per series (deterministic).
 template <bool Dict>
-__global__ __launch_bounds__(kReconThreads, 8) void k_recon(Src src, const int64_t *__restrict__ piece_off,
+__global__ __launch_bounds__(kReconThreads, 4) void k_recon(Src src, const int64_t *__restrict__ piece_off,
                                                          const int64_t *__restrict__ out_off, int64_t n_series,
                                                          const double *__restrict__ t0, double *__restrict__ out,
                                                          int64_t *__restrict__ lhat,
@@ -279,53 +293,80 @@ __global__ __launch_bounds__(kReconThreads, 8) void k_recon(Src src, const int64
                 err = d * d;
             }
         }
-        u128 carryC = 0;
-        int64_t carryS = 0;
+        int64_t carryH = 0, carryS = 0;
+        uint64_t carryL = 0;
         double V = 0.0;
         // loads of the next chunk (raw_n) and of the symbols two chunks
         // ahead (tag_n); indices past the series' last piece are clamped to
         // it and their results never used
         auto clampj = [&](int64_t j) -> int64_t { return j < b ? j : b - 1; };
+        // symbols are loaded kTagAhead chunks ahead (from HBM), the centers
+        // they select one chunk ahead (from the cache-resident dictionary)
+        constexpr int kTagAhead = 3;
         Src::Raw raw_n{0.0, 0.0, 0, false};
-        int32_t tag_n = 0;
+        int32_t tg0 = 0, tg1 = 0, tg2 = 0, tg3 = 0;
         if (producer) {
             V = t0[s];
             if (lane == 0 && out_off[s + 1] > o) out[o] = V;
             if (nch > 0) {
                 const int64_t j = a + lane;
                 raw_n = src.fetch<Dict>(clampj(j), src.tag_at<Dict>(clampj(j)));
-                tag_n = src.tag_at<Dict>(clampj(j + kWave));
+                tg1 = src.tag_at<Dict>(clampj(j + kWave));
+                tg2 = src.tag_at<Dict>(clampj(j + 2 * kWave));
+                tg3 = src.tag_at<Dict>(clampj(j + 3 * kWave));
             }
         }
-        // chunk t: cur holds its loads, tcur the symbols of chunk t + 1; the
-        // step loads chunk t + 1 into nxt and the symbols of chunk t + 2 into
-        // tnxt.  The loop below alternates the two register sets, so a load
-        // lands in a register nothing reads until the next chunk.
-        auto step = [&](int64_t t, const Src::Raw &cur, Src::Raw &nxt, const int32_t &tcur, int32_t &tnxt) {
+        // chunk t: cur holds its loads, tnext the symbols of chunk t + 1; the
+        // step loads chunk t + 1 into nxt and the symbols of chunk
+        // t + 1 + kTagAhead into tload (the register that held chunk t's).
+        // The loop below rotates the register sets, so a load lands in a
+        // register nothing reads until it is due.
+        auto step = [&](int64_t t, const Src::Raw &cur, Src::Raw &nxt, const int32_t &tnext, int32_t &tload) {
             if (producer && t < nch) {
                 const int64_t j0 = a + t * kWave;
                 const int64_t j = j0 + lane;
                 u128 lt = 0;
                 double it = 0.0;
-                // the next chunk's loads, consumed one chunk later
-                nxt = src.fetch<Dict>(clampj(j + kWave), tcur);
-                tnxt = src.tag_at<Dict>(clampj(j + 2 * kWave));
+                nxt = src.fetch<Dict>(clampj(j + kWave), tnext);
+                tload = src.tag_at<Dict>(clampj(j + (1 + kTagAhead) * kWave));
                 if (j < b) {
                     bool ok = true;
                     src.convert(cur, lt, it, ok);
                 }
-                // inclusive scan of the fixed-point center lengths
-                u128 C = wave_incl_scan_u128(lt) + carryC;
-                const int64_t S = fixed_round(C);
+                const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
+                ReconChunk &B = buf[t & 1];
+                // inclusive scan of the fixed-point center lengths on top of
+                // the carry carryH * 2^52 + carryL (carryL < 2^52)
+                constexpr uint64_t kFrac = (1ull << 52) - 1;
+                int64_t S;
+                if (!ballot((lt >> 77) != 0)) {
+                    // limbs of lt = h * 2^52 + m * 2^26 + q, h < 2^25 and
+                    // m, q < 2^26: the scans stay below 2^32
+                    const uint32_t hs = wave_incl_scan_u32((uint32_t)(lt >> 52));
+                    const uint32_t ms = wave_incl_scan_u32((uint32_t)(lt >> 26) & ((1u << 26) - 1));
+                    const uint32_t qs = wave_incl_scan_u32((uint32_t)lt & ((1u << 26) - 1));
+                    const uint64_t low = ((uint64_t)ms << 26) + qs + carryL;  // below 2^59
+                    S = carryH + (int64_t)hs + (int64_t)((low + (1ull << 51)) >> 52);
+                    const uint64_t lowc = (uint64_t)readlane_i64((int64_t)low, cnt - 1);
+                    carryH += (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)hs, cnt - 1) + (int64_t)(lowc >> 52);
+                    carryL = lowc & kFrac;
+                } else {
+                    const u128 C = wave_incl_scan_u128(lt) + (((u128)(uint64_t)carryH << 52) | carryL);
+                    S = fixed_round(C);
+                    const u128 Cc = readlane_u128(C, cnt - 1);
+                    carryH = (int64_t)(Cc >> 52);
+                    carryL = (uint64_t)Cc & kFrac;
+                }
                 const int64_t Sp = wave_shr1_i64(S, carryS);
                 const int64_t lh = S - Sp;
+                B.beg[lane] = Sp;
+                B.end[lane] = S;
+                carryS = readlane_i64(S, cnt - 1);
                 // sequential running value, V_j on lane j: every step moves
                 // each lane's value one lane up (lane 0 takes V before the
                 // chunk) and adds the lane's own increment.  After cnt steps
                 // lanes 0..cnt-1 hold V_0..V_{cnt-1}, each the one binary64
                 // addition V_{j-1} + inc~_j of the left-to-right evaluation.
-                const int cnt = (int)((b - j0) < kWave ? (b - j0) : kWave);
-                ReconChunk &B = buf[t & 1];
                 if (lane == 0) B.vin = V;
                 // (prev keeps V on lane 0 from one step to the next, so the
                 // shift writes it in place)
@@ -344,11 +385,7 @@ __global__ __launch_bounds__(kReconThreads, 8) void k_recon(Src src, const int64
                 }
                 B.vme[lane] = Vl;
                 V = readlane_f64(Vl, cnt - 1);
-                B.beg[lane] = Sp;
-                B.end[lane] = S;
                 B.slope[lane] = it / (double)lh;
-                carryC = readlane_u128(C, cnt - 1);
-                carryS = readlane_i64(S, cnt - 1);
             }
             if (!producer && t > 0) {
                 const int64_t tc = t - 1;
@@ -369,18 +406,18 @@ __global__ __launch_bounds__(kReconThreads, 8) void k_recon(Src src, const int64
                     for (int u = 0; u < kAhead; ++u) {
                         const int64_t r = r0 + (int64_t)u * kFillThreads;
                         if (r > hi) break;
-                        // first piece whose end is at or after point r
-                        int L = 0, H = cnt - 1;
-                        while (L < H) {
-                            const int M = (L + H) >> 1;
-                            if (B.end[M] >= r)
-                                H = M;
-                            else
-                                L = M + 1;
-                        }
+                        // first piece whose end is at or after point r: the
+                        // ends do not decrease and lanes past the chunk's
+                        // last piece hold its end (hi >= r), so a fixed
+                        // six-step search over all 64 entries finds it
+                        int L = 0;
+#pragma unroll
+                        for (int step = kWave / 2; step > 0; step >>= 1)
+                            L += B.end[L + step - 1] < r ? step : 0;
                         const double vprev = L > 0 ? B.vme[L - 1] : B.vin;
-                        const double vr =
-                            (r == B.end[L]) ? B.vme[L] : vprev + B.slope[L] * (double)(r - B.beg[L]);
+                        // the offset inside a piece is below 2^31 (a series' point count)
+                        const double vr = (r == B.end[L]) ? B.vme[L]
+                                                          : vprev + B.slope[L] * (double)(int32_t)(r - B.beg[L]);
                         out[o + r] = vr;
                         if (r < m_err) {  // each thread adds its points in increasing r
                             const double d = orig[u] - vr;
@@ -394,10 +431,12 @@ __global__ __launch_bounds__(kReconThreads, 8) void k_recon(Src src, const int64
             __syncthreads();
         };
         Src::Raw raw_b{0.0, 0.0, 0, false};
-        int32_t tag_b = 0;
-        for (int64_t t = 0; t <= nch; t += 2) {
-            step(t, raw_n, raw_b, tag_n, tag_b);
-            if (t + 1 <= nch) step(t + 1, raw_b, raw_n, tag_b, tag_n);
+        static_assert(kTagAhead == 3, "the rotation below holds four symbol registers");
+        for (int64_t t = 0; t <= nch; t += 4) {
+            step(t, raw_n, raw_b, tg1, tg0);
+            if (t + 1 <= nch) step(t + 1, raw_b, raw_n, tg2, tg1);
+            if (t + 2 <= nch) step(t + 2, raw_n, raw_b, tg3, tg2);
+            if (t + 3 <= nch) step(t + 3, raw_b, raw_n, tg0, tg3);
         }
         if (values && !producer) {
             const double tot = wave_tree_sum(err);

@@ -407,6 +407,35 @@ def test_reconstruct_half_lengths():
     assert r["out"].cpu().tolist() == [0.0, 0.5, 1.0, 0.5, 0.0, 0.5, 1.0]
 
 
+def test_reconstruct_long_center_lengths():
+    """A center length of 2^25 + 3/4 among short ones: the 64-piece chunks
+    that hold it scan the fixed-point lengths in 128 bits, the others in
+    32-bit limbs, and the carry passes between the two forms (series 0:
+    chunks 0, 2 and 3 short, chunk 1 long; series 1: its first chunk long)."""
+    import paper_2401_00109_amd as J
+    rng = np.random.default_rng(7)
+    cl = np.array([1.5, 2.25, 3.0, 2.0 ** 25 + 0.75])
+    ci = np.array([1.0, -0.5, 0.25, 3.0])
+    sym = rng.integers(0, 3, size=330).astype(np.int32)
+    sym[100] = 3
+    sym[250] = 3
+    po = np.array([0, 200, 330], np.int64)
+    off = np.array([0, 1000, 2000], np.int64)
+    t0 = np.array([0.5, -2.0])
+    values = rng.normal(size=2000)
+    out, oo, lhat, sse, cnt = O.reconstruct(sym, po, off, t0, cl, ci, orig=values)
+    say(f"reconstruct with two pieces of 2^25 points: {out.size} points")
+    d = J.Dictionary.from_host(1.0, 1.0, 1.0, 0.1, cl, ci, cl, ci, device=DEV)
+    r = J.reconstruct(to_dev(sym), to_dev(po), to_dev(off), to_dev(t0), d, values=to_dev(values), want_lhat=True)
+    assert r["status"] == 0
+    np.testing.assert_array_equal(r["out_off"].cpu().numpy(), oo)
+    np.testing.assert_array_equal(r["lhat"][: sym.size].cpu().numpy(), lhat)
+    assert lhat[100] >= 2 ** 25 and lhat[250] >= 2 ** 25
+    np.testing.assert_array_equal(r["out"][: out.size].cpu().numpy().view(np.uint64), out.view(np.uint64))
+    np.testing.assert_array_equal(r["cnt"].cpu().numpy()[:2], cnt)
+    np.testing.assert_allclose(r["sse"].cpu().numpy()[:2], sse, rtol=1e-12, atol=1e-300)
+
+
 # ------------------------------------------------------------------ graph plan
 def test_plan_graph_replays_match_eager():
     import paper_2401_00109_amd as J
