@@ -53,7 +53,10 @@ def timing_name(kernel: str) -> str:
     if not m:
         return kernel.split("(")[0][-60:]
     base, targs = m.group(1), (m.group(2) or "")
-    if base in ("k_compress", "k_compress1"):
+    if base == "k_compress1":  # <Norm, Grouped>
+        norm = targs.strip("<>").split(",")[0].strip()
+        return "k_compress_znorm" if norm in ("true", "(bool)1") else "k_compress<W>"
+    if base == "k_compress":
         return "k_compress_znorm" if ("true" in targs or "(bool)1" in targs) else "k_compress<W>"
     if base == "k_onesweep":  # <0, ...>: the main sort's passes; the others: every other radix sort
         return base + ("" if targs.startswith("<0") else "_aux")
@@ -146,7 +149,9 @@ def main() -> int:
     write = load_counter(args.write, "WRITE_SIZE")
     ff, wf = calibration(fetch), calibration(write)
 
-    traffic = {}
+    # per kernel as rocprof names it (template forms apart); a timing name
+    # that covers several forms keeps the one launched most often
+    by_name = {}
     for name in set(fetch) | set(write):
         if "jabba" not in name:
             continue
@@ -154,11 +159,16 @@ def main() -> int:
         w = write.get(name, [])
         fb = (sum(f) / len(f) * 1024.0 * ff) if (f and ff) else None
         wb = (sum(w) / len(w) * 1024.0 * wf) if (w and wf) else None
+        by_name[name] = {"rocprof_name": name[:name.find("(", name.find("::k_"))] if "::k_" in name else name[:80],
+                         "dispatches": len(f),
+                         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                         "bytes_per_launch": (fb or 0.0) + (wb or 0.0) if (fb is not None and wb is not None)
+                         else None}
+    traffic = {}
+    for name, e in sorted(by_name.items()):
         tn = timing_name(name)
-        traffic[tn] = {"rocprof_name": name[:name.find("(", name.find("::k_"))] if "::k_" in name else name[:80],
-                       "dispatches": len(f),
-                       "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-                       "bytes_per_launch": (fb or 0.0) + (wb or 0.0) if (fb is not None and wb is not None) else None}
+        if tn not in traffic or e["dispatches"] > traffic[tn]["dispatches"]:
+            traffic[tn] = e
 
     os.makedirs(args.out, exist_ok=True)
     with open(os.path.join(args.out, f"traffic_{args.workload}.json"), "w") as fh:
@@ -171,7 +181,7 @@ def main() -> int:
     # every kernel of the library that has both figures
     tot_bytes = tot_ns = 0.0
     for r in stats:
-        t = traffic.get(timing_name(r["Name"]), {})
+        t = by_name.get(r["Name"]) or traffic.get(timing_name(r["Name"]), {})
         if "jabba" in r["Name"] and t.get("bytes_per_launch") is not None:
             tot_bytes += t["bytes_per_launch"] * float(r["Calls"])
             tot_ns += float(r["TotalDurationNs"])
@@ -188,7 +198,7 @@ def main() -> int:
              "|---|---|---|---|---|---|---|---|---|"]
     for r in stats[:24]:
         tn = timing_name(r["Name"])
-        t = traffic.get(tn, {})
+        t = by_name.get(r["Name"]) or traffic.get(tn, {})
         fb, wb = t.get("fetch_bytes_per_launch"), t.get("write_bytes_per_launch")
         bl = t.get("bytes_per_launch")
         avg_ns = float(r["AverageNs"])
