@@ -175,6 +175,39 @@ def test_compress_exact_path_in_later_domains():
     assert ol.size == 40 * 12_500 and np.count_nonzero(ol == 7) == 40 and np.count_nonzero(ol == 8) == 40 * 12_499
 
 
+@pytest.mark.parametrize("znorm", [False, True])
+def test_compress_grouped_and_single_piece_stores(znorm):
+    """Tens of thousands of short domains: with one wavefront per compute
+    unit they outnumber the lanes, and the one-lane kernel keeps the pieces
+    in groups of four staging slots (partial groups at both ends of every
+    domain); with the widest launch the lanes outnumber them and each piece
+    is stored at once.  Domains of 7 intervals over series of 1 to 400
+    points give every alignment of a domain's first slot and every piece
+    count modulo 4.  Both launches equal the oracle, z-normalised too."""
+    rng = np.random.default_rng(11)
+    lengths = rng.integers(1, 400, size=2000)
+    vals, off = pack([3.0 + np.cumsum(rng.standard_normal(int(n))) for n in lengths])
+    D = 7
+    src = vals
+    if znorm:
+        src, om, osd = O.znorm(vals, off)
+    for tol in (0.0, 0.5):
+        ol, oi, opo = O.compress(src, off, D, tol)
+        for tuning in ({"lanes_per_domain": 1, "waves_per_block": 1, "blocks_per_cu": 1},
+                       {"lanes_per_domain": 1, "waves_per_block": 4, "blocks_per_cu": 32}):
+            say(f"compress {off[-1]} points in {off[-1] // D + len(lengths)} domains or fewer, tol={tol}, "
+                f"znorm={znorm}, {tuning}")
+            r = gpu_compress(vals, off, D, tol, tuning=tuning, znorm=znorm)
+            ln, inc, po, st = r[:4]
+            assert st == 0
+            if znorm:
+                np.testing.assert_array_equal(r[4].view(np.uint64), om.view(np.uint64))
+                np.testing.assert_array_equal(r[5].view(np.uint64), osd.view(np.uint64))
+            np.testing.assert_array_equal(po, opo)
+            np.testing.assert_array_equal(ln, ol)
+            np.testing.assert_array_equal(inc.view(np.uint64), oi.view(np.uint64))
+
+
 def test_compress_empty_input():
     say("compress empty input")
     ln, inc, po, st = gpu_compress(np.zeros(0), np.zeros(1, np.int64), 10, 0.1)
@@ -405,6 +438,35 @@ def test_reconstruct_half_lengths():
     r = J.reconstruct(to_dev(sym), to_dev(po), to_dev(off), to_dev(np.array([0.0])), d, want_lhat=True)
     assert r["lhat"][:3].cpu().tolist() == [2, 2, 2]
     assert r["out"].cpu().tolist() == [0.0, 0.5, 1.0, 0.5, 0.0, 0.5, 1.0]
+
+
+def test_reconstruct_every_chunk_count():
+    """Series of 0 to 385 pieces: every count of 64-piece chunks from 0 to 7
+    (the symbols are loaded three chunks ahead through four rotating
+    registers, so each count ends the rotation at a different register),
+    with counts just below, at and above each multiple of 64."""
+    import paper_2401_00109_amd as J
+    rng = np.random.default_rng(12)
+    counts = [0, 1, 2, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257, 319, 320, 321, 383, 384, 385]
+    k = 37
+    cl = 1.0 + rng.integers(0, 16, size=k) / 4.0
+    ci = rng.standard_normal(k)
+    sym = rng.integers(0, k, size=sum(counts)).astype(np.int32)
+    po = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n = [int(c * 3 + 1) for c in counts]
+    off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    values = rng.standard_normal(int(off[-1]))
+    t0 = values[np.minimum(off[:-1], off[-1] - 1)]
+    out, oo, lhat, sse, cnt = O.reconstruct(sym, po, off, t0, cl, ci, orig=values)
+    say(f"reconstruct {len(counts)} series of 0 to {max(counts)} pieces")
+    d = J.Dictionary.from_host(1.0, 1.0, 1.0, 0.1, cl, ci, cl, ci, device=DEV)
+    r = J.reconstruct(to_dev(sym), to_dev(po), to_dev(off), to_dev(t0), d, values=to_dev(values), want_lhat=True)
+    assert r["status"] == 0
+    np.testing.assert_array_equal(r["out_off"].cpu().numpy(), oo)
+    np.testing.assert_array_equal(r["lhat"][: sym.size].cpu().numpy(), lhat)
+    np.testing.assert_array_equal(r["out"][: out.size].cpu().numpy().view(np.uint64), out.view(np.uint64))
+    np.testing.assert_array_equal(r["cnt"].cpu().numpy()[: len(counts)], cnt)
+    np.testing.assert_allclose(r["sse"].cpu().numpy()[: len(counts)], sse, rtol=1e-12, atol=1e-300)
 
 
 def test_reconstruct_long_center_lengths():
