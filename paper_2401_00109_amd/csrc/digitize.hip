@@ -1259,13 +1259,41 @@ __global__ void k_compact_starts(const DigState *ds, const uint32_t *__restrict_
                                  int32_t *__restrict__ spos, int64_t *__restrict__ g_count) {
     const int64_t n = ds->n;
     if (blockIdx.x == 0 && threadIdx.x == 0) *g_count = (int64_t)sidx[n];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        if (!flag[p]) continue;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    auto emit = [&](int64_t p) {
         const uint32_t g = sidx[p];
         gk[g] = sk[p];
         gx[g] = sx[p];
         gy[g] = sy[p];
         spos[g] = (int32_t)p;
+    };
+    if (((uintptr_t)flag & 15) != 0) {
+        for (int64_t p = tid; p < n; p += stride)
+            if (flag[p]) emit(p);
+        return;
+    }
+    // starts are sparse: four flags per lane in one 16-byte load, the rest
+    // read only for the flagged positions
+    const uint4 *flag4 = reinterpret_cast<const uint4 *>(flag);
+    const int64_t n4 = (n + 3) >> 2;
+    for (int64_t q = tid; q < n4; q += stride) {
+        const int64_t p0 = q << 2;
+        uint32_t f[4];
+        if (p0 + 4 <= n) {
+            const uint4 v = flag4[q];
+            f[0] = v.x;
+            f[1] = v.y;
+            f[2] = v.z;
+            f[3] = v.w;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) f[u] = p0 + u < n ? flag[p0 + u] : 0u;
+        }
+        if ((f[0] | f[1] | f[2] | f[3]) == 0u) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (f[u]) emit(p0 + u);
     }
 }
 

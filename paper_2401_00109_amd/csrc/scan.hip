@@ -109,18 +109,48 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const Tin *__restric
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *grand;
     if (base >= n) return;
-    // each thread owns kScanItems consecutive elements of the tile
+    // each thread owns kScanItems consecutive elements of the tile; a full
+    // tile of 4-byte types on 16-byte boundaries moves them as two 16-byte
+    // loads and stores per thread
     const int64_t my0 = base + (int64_t)threadIdx.x * kScanItems;
+    bool vec = false;
+    if constexpr (sizeof(Tin) == 4 && sizeof(Tout) == 4 && kScanItems == 8)
+        vec = base + kTile <= n && ((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 15) == 0;
     Tout v[kScanItems];
     Tout acc = 0;
+    if (vec) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + my0);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        int64_t idx = my0 + i;
-        v[i] = idx < n ? (Tout)in[idx] : (Tout)0;
-        acc += v[i];
+        for (int i = 0; i < kScanItems; ++i) {
+            Tin t;
+            __builtin_memcpy(&t, &w[i], sizeof(t));
+            v[i] = (Tout)t;
+            acc += v[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            int64_t idx = my0 + i;
+            v[i] = idx < n ? (Tout)in[idx] : (Tout)0;
+            acc += v[i];
+        }
     }
     Tout tot;
     Tout run = block_exclusive_scan<Tout>(acc, lds, &tot) + sums[blockIdx.x];
+    if (vec) {
+        uint32_t w[8];
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            __builtin_memcpy(&w[i], &run, sizeof(uint32_t));
+            run += v[i];
+        }
+        uint4 *q = reinterpret_cast<uint4 *>(out + my0);
+        q[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        q[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         int64_t idx = my0 + i;
