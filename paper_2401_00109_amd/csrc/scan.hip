@@ -52,7 +52,20 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const Tin *__restric
     const int64_t n = live_n(n_dev, n_max);
     const int64_t base = (int64_t)blockIdx.x * kTile;
     Tout acc = 0;
-    if (base < n) {
+    bool vec = false;
+    if constexpr (sizeof(Tin) == 4 && kScanItems == 8)
+        vec = base + kTile <= n && ((uintptr_t)in & 15) == 0;
+    if (vec) {  // a full tile of 4-byte values: two 16-byte loads per thread (an exact sum, any order)
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base + (int64_t)threadIdx.x * kScanItems);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            Tin t;
+            __builtin_memcpy(&t, &w[i], sizeof(t));
+            acc += (Tout)t;
+        }
+    } else if (base < n) {
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
