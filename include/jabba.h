@@ -432,10 +432,15 @@ int jabba_reconstruct_size(const int32_t *symbols, const int64_t *piece_off, con
  * (Sec. 3.3, MSE = sum(sse)/sum(cnt)).  dict->capacity >= 1, else
  * JABBA_EINVAL; a symbol outside [0, capacity) reads as length 1, increment 0
  * (jabba_reconstruct_size flags it in the device status).
+ * workspace: jabba_reconstruct_workspace(n_series) bytes (JABBA_ENOMEM if
+ * smaller; the one given to jabba_reconstruct_size may be passed again, its
+ * status word is kept); it holds the order in which series are taken, the
+ * longest first, which changes no output.
  */
 int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off, int64_t n_series,
                       const double *t0, const jabba_dict *dict, const int64_t *out_off, double *out, int64_t *lhat,
-                      const double *values, double *sse, int64_t *cnt, void *stream);
+                      const double *values, double *sse, int64_t *cnt, void *workspace, size_t workspace_bytes,
+                      void *stream);
 
 /*
  * Mean squared error of a reconstruction (Sec. 3.3): mse[0] (device) =

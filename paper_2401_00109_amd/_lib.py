@@ -102,7 +102,7 @@ def lib() -> C.CDLL:
             L.jabba_encode_noalloc.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P]
             L.jabba_reconstruct_workspace.argtypes = [I64, C.POINTER(SZ)]
             L.jabba_reconstruct_size.argtypes = [P, P, P, I64, C.POINTER(Dict), P, P, SZ, P]
-            L.jabba_reconstruct.argtypes = [P, P, P, I64, P, C.POINTER(Dict), P, P, P, P, P, P, P]
+            L.jabba_reconstruct.argtypes = [P, P, P, I64, P, C.POINTER(Dict), P, P, P, P, P, P, P, SZ, P]
             L.jabba_reconstruct_mse.argtypes = [P, P, I64, P, P]
             L.jabba_reconstruct_pieces.argtypes = [P, P, P, P, I64, P, P, P, P, SZ, P]
             L.jabba_workspace_status.argtypes = [P, P, C.POINTER(C.c_int32)]

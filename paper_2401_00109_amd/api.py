@@ -404,7 +404,8 @@ def reconstruct(symbols: torch.Tensor, piece_off: torch.Tensor, series_off: torc
         sse = torch.empty(max(ns, 1), dtype=torch.float64, device=dev)
         cnt = torch.empty(max(ns, 1), dtype=torch.int64, device=dev)
     L.check(L.lib().jabba_reconstruct(_p(symbols), _p(piece_off), _p(series_off), ns, _p(t0), C.byref(d),
-                                      _p(out_off), _p(out), _p(lhat), _p(values), _p(sse), _p(cnt), st),
+                                      _p(out_off), _p(out), _p(lhat), _p(values), _p(sse), _p(cnt), _p(ws),
+                                      ws.numel(), st),
             "jabba_reconstruct")
     return {"out": out[:total], "out_off": out_off, "lhat": lhat, "sse": sse, "cnt": cnt, "status": status}
 
@@ -603,7 +604,8 @@ class Reconstructor:
         L.check(L.lib().jabba_reconstruct(_p(symbols), _p(self.piece_off), _p(self.series_off), self.ns, _p(self.t0),
                                           C.byref(d), _p(self.out_off), _p(self.out), None, _p(v),
                                           _p(self.sse) if v is not None else None,
-                                          _p(self.cnt) if v is not None else None, _stream(stream)),
+                                          _p(self.cnt) if v is not None else None, _p(self.ws), self.ws.numel(),
+                                          _stream(stream)),
                 "jabba_reconstruct")
 
     def mse(self, stream=None) -> float:

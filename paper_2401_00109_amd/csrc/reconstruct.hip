@@ -200,10 +200,12 @@ struct Src {
 
 __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__restrict__ piece_off,
                                                      const int64_t *__restrict__ series_off, int64_t n_series,
-                                                     int64_t *__restrict__ cnt, int32_t *status) {
+                                                     const int32_t *__restrict__ order, int64_t *__restrict__ cnt,
+                                                     int32_t *status) {
     const int lane = lane_id();
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n_series; s += waves) {
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < n_series; i += waves) {
+        const int64_t s = order[i];
         const int64_t a = piece_off[s], b = piece_off[s + 1];
         if (b <= a) {
             if (lane == 0) cnt[s] = (series_off[s + 1] - series_off[s]) >= 1 ? 1 : 0;
@@ -272,12 +274,14 @@ __global__ __launch_bounds__(kReconThreads, 4) void k_recon(Src src, const int64
                                                          int64_t *__restrict__ lhat,
                                                          const int64_t *__restrict__ series_off,
                                                          const double *__restrict__ values,
-                                                         double *__restrict__ sse, int64_t *__restrict__ sse_cnt) {
+                                                         double *__restrict__ sse, int64_t *__restrict__ sse_cnt,
+                                                         const int32_t *__restrict__ order) {
     __shared__ ReconChunk buf[2];
     const int lane = lane_id();
     // uniform per wavefront, and known to be: the roles branch on a scalar
     const bool producer = __builtin_amdgcn_readfirstlane(threadIdx.x) < kWave;
-    for (int64_t s = blockIdx.x; s < n_series; s += gridDim.x) {
+    for (int64_t i = blockIdx.x; i < n_series; i += gridDim.x) {
+        const int64_t s = order[i];
         const int64_t a = piece_off[s], b = piece_off[s + 1];
         const int64_t o = out_off[s];
         const int64_t nch = b > a ? (b - a + kWave - 1) / kWave : 0;
@@ -452,6 +456,78 @@ __global__ void k_recon_prep(int32_t *status) {
     if (threadIdx.x == 0) status[0] = 0;
 }
 
+// Series order for the per-series kernels: the longest first.  One workgroup
+// (or wavefront) per series is started as earlier ones end, so a long series
+// started late sets the kernel's end; taking the series by descending
+// power-of-two class of their 64-piece chunk count bounds that tail by the
+// shortest class.  A counting sort: class counts, then each series a slot in
+// its class's range (the order inside a class depends on timing; nothing
+// computed depends on it, since every series writes only its own outputs).
+constexpr int kOrderClasses = 34;  // 1 + floor(log2(chunks)) below 2^32, and one for series without pieces
+constexpr int kOrderThreads = 256;
+
+// class 32 - floor(log2(chunks)) (0 beyond 2^32 chunks), the last for none
+__device__ __forceinline__ int order_class(const int64_t *__restrict__ piece_off, int64_t s) {
+    const int64_t nch = (piece_off[s + 1] - piece_off[s] + kWave - 1) / kWave;
+    if (nch <= 0) return kOrderClasses - 1;
+    const int lg = 63 - __clzll((unsigned long long)nch);
+    return lg < 32 ? 32 - lg : 0;
+}
+
+__global__ void k_order_prep(uint32_t *hist, uint32_t *cursor) {
+    if (threadIdx.x < kOrderClasses) {
+        hist[threadIdx.x] = 0u;
+        cursor[threadIdx.x] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_count(const int64_t *__restrict__ piece_off,
+                                                               int64_t n_series, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kOrderClasses];
+    if (threadIdx.x < kOrderClasses) h[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t s = (int64_t)blockIdx.x * kOrderThreads + threadIdx.x; s < n_series;
+         s += (int64_t)gridDim.x * kOrderThreads)
+        atomicAdd(&h[order_class(piece_off, s)], 1u);
+    __syncthreads();
+    if (threadIdx.x < kOrderClasses && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// one series per thread: its rank among the workgroup's series of its class
+// (LDS), the workgroup's range in the class (one global atomic per class)
+__global__ __launch_bounds__(kOrderThreads) void k_order_scatter(const int64_t *__restrict__ piece_off,
+                                                                 int64_t n_series, const uint32_t *__restrict__ hist,
+                                                                 uint32_t *__restrict__ cursor,
+                                                                 int32_t *__restrict__ order) {
+    __shared__ uint32_t base[kOrderClasses];
+    __shared__ uint32_t h[kOrderClasses];
+    __shared__ uint32_t at[kOrderClasses];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int c = 0; c < kOrderClasses; ++c) {
+            base[c] = run;
+            run += hist[c];
+        }
+    }
+    for (int64_t s0 = (int64_t)blockIdx.x * kOrderThreads; s0 < n_series; s0 += (int64_t)gridDim.x * kOrderThreads) {
+        if (threadIdx.x < kOrderClasses) h[threadIdx.x] = 0u;
+        __syncthreads();
+        const int64_t s = s0 + threadIdx.x;
+        int c = 0;
+        uint32_t r = 0;
+        if (s < n_series) {
+            c = order_class(piece_off, s);
+            r = atomicAdd(&h[c], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < kOrderClasses && h[threadIdx.x])
+            at[threadIdx.x] = base[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+        if (s < n_series) order[at[c] + r] = (int32_t)s;
+        __syncthreads();
+    }
+}
+
 // The grids below hold one wavefront (k_recon_count) or one workgroup
 // (k_recon) per series and no more than that: series lengths can differ by
 // orders of magnitude, and the dispatcher starting each workgroup as an
@@ -478,6 +554,8 @@ struct ReconWs {
     int32_t *status;
     int64_t *cnt;
     void *scan_ws;
+    uint32_t *hist, *cursor;
+    int32_t *order;
     size_t bytes;
 };
 
@@ -487,8 +565,27 @@ ReconWs carve_recon(void *ws, int64_t n_series) {
     w.status = c.take<int32_t>(64);
     w.cnt = c.take<int64_t>(n_series + 1);
     w.scan_ws = c.take<char>(scan_workspace(n_series + 1));
+    w.hist = c.take<uint32_t>(64);
+    w.cursor = c.take<uint32_t>(64);
+    w.order = c.take<int32_t>(n_series);
     w.bytes = c.bytes();
     return w;
+}
+
+// w.order <- the series, longest class first
+int series_order(const ReconWs &w, const int64_t *piece_off, int64_t n_series, hipStream_t st) {
+    if (n_series <= 0) return JABBA_OK;
+    int64_t blocks = (n_series + kOrderThreads - 1) / kOrderThreads;
+    const int64_t cap = (int64_t)device_cu_count() * 4;
+    if (blocks > cap) blocks = cap;
+    JB_LAUNCH(k_order_prep, dim3(1), dim3(64), 0, st, w.hist, w.cursor);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_order_count, dim3((unsigned)blocks), dim3(kOrderThreads), 0, st, piece_off, n_series, w.hist);
+    JB_LAUNCH_CHECK();
+    JB_LAUNCH(k_order_scatter, dim3((unsigned)blocks), dim3(kOrderThreads), 0, st, piece_off, n_series, w.hist,
+              w.cursor, w.order);
+    JB_LAUNCH_CHECK();
+    return JABBA_OK;
 }
 
 int sizes(const Src &src, const int64_t *piece_off, const int64_t *series_off, int64_t n_series, int64_t *out_off,
@@ -501,8 +598,10 @@ int sizes(const Src &src, const int64_t *piece_off, const int64_t *series_off, i
     JB_LAUNCH(k_recon_prep, dim3(1), dim3(64), 0, st, w.status);
     JB_LAUNCH_CHECK();
     if (n_series > 0) {
+        const int rc = series_order(w, piece_off, n_series, st);
+        if (rc) return rc;
         JB_LAUNCH(k_recon_count, dim3(waves_grid(n_series)), dim3(256), 0, st, src, piece_off, series_off,
-                           n_series, w.cnt, w.status);
+                           n_series, w.order, w.cnt, w.status);
         JB_LAUNCH_CHECK();
     }
     return scan_i64_to_i64(w.cnt, out_off, nullptr, n_series, w.scan_ws, st);
@@ -577,7 +676,7 @@ extern "C" int jabba_reconstruct_size(const int32_t *symbols, const int64_t *pie
 extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_off, const int64_t *series_off,
                                  int64_t n_series, const double *t0, const jabba_dict *dict, const int64_t *out_off,
                                  double *out, int64_t *lhat, const double *values, double *sse, int64_t *cnt,
-                                 void *stream) {
+                                 void *workspace, size_t workspace_bytes, void *stream) {
     if (!dict || !dict->center_len || !dict->center_inc || n_series < 0 || !piece_off || !out_off) return JABBA_EINVAL;
     if (dict->capacity < 1) return JABBA_EINVAL;
     if (n_series == 0) return JABBA_OK;
@@ -585,9 +684,13 @@ extern "C" int jabba_reconstruct(const int32_t *symbols, const int64_t *piece_of
     hipStream_t st = (hipStream_t)stream;
     Src src{symbols, dict->center_len, dict->center_inc, dict->capacity, nullptr, nullptr};
     if (values && (!sse || !cnt)) return JABBA_EINVAL;
+    if (!workspace || workspace_bytes < carve_recon(nullptr, n_series).bytes) return JABBA_ENOMEM;
     JB_DEVICE_CHECK();
+    const ReconWs w = carve_recon(workspace, n_series);
+    const int rc = series_order(w, piece_off, n_series, st);
+    if (rc) return rc;
     JB_LAUNCH_NAMED("k_recon", k_recon<true>, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src, piece_off,
-                    out_off, n_series, t0, out, lhat, series_off, values, sse, cnt);
+                    out_off, n_series, t0, out, lhat, series_off, values, sse, cnt, w.order);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
@@ -601,9 +704,10 @@ extern "C" int jabba_reconstruct_pieces(const int32_t *len, const double *inc, c
     int rc = sizes(src, piece_off, series_off, n_series, out_off, workspace, workspace_bytes, st);
     if (rc || n_series == 0) return rc;
     if (!t0 || !out) return JABBA_EINVAL;
+    // the size pass above left the series order in the workspace
     JB_LAUNCH_NAMED("k_recon_pieces", k_recon<false>, dim3(series_grid(n_series)), dim3(kReconThreads), 0, st, src,
                     piece_off, out_off, n_series, t0, out, (int64_t *)nullptr, series_off, (const double *)nullptr,
-                    (double *)nullptr, (int64_t *)nullptr);
+                    (double *)nullptr, (int64_t *)nullptr, carve_recon(workspace, n_series).order);
     JB_LAUNCH_CHECK();
     return JABBA_OK;
 }
