@@ -875,8 +875,12 @@ __global__ __launch_bounds__(1024) void k_stage1(const int64_t *__restrict__ cut
                                                  uint32_t *__restrict__ flag, int32_t *__restrict__ start_blk) {
     extern __shared__ ActLds act_lds[];
     const int wave = threadIdx.x / kWave;
-    const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-    if (blk >= nblk_max) return;
+    // blocks in descending key order: the last blocks (large keys, sparse
+    // points, many starts each) take the longest, and are started first so
+    // that none of them is left to run alone at the end
+    const int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+    if (idx >= nblk_max) return;
+    const int64_t blk = nblk_max - 1 - idx;
     const int64_t lo = cuts[blk], hi = cuts[blk + 1];
     if (lo >= hi) return;
     Active A{&act_lds[wave], glist + lo, 0, 0};
