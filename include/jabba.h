@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define JABBA_ABI_VERSION 3
+#define JABBA_ABI_VERSION 4
 
 enum jabba_status {
     JABBA_OK = 0,

@@ -246,9 +246,10 @@ __global__ __launch_bounds__(256) void k_recon_count(Src src, const int64_t *__r
     }
 }
 
-// One workgroup per series.  Wavefront 0 produces chunks of 64 pieces (the
-// fixed-point scan of the lengths and the sequential values) into LDS while
-// the next chunk's loads are in flight; wavefront 1 fills the points of the
+// One workgroup per series, the series taken in the order given (longest
+// first).  Wavefront 0 produces chunks of 64 pieces (the fixed-point scan of
+// the lengths and the sequential values) into LDS while the next chunks'
+// loads are in flight; wavefront 1 fills the points of the
 // previous chunk, one point per thread (coalesced stores), with the original
 // values for the squared error loaded four points at a time.  The two LDS
 // buffers alternate, one barrier per chunk.

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     L = _lib.lib()
     for name in declared_functions():
         assert hasattr(L, name), f"{name} declared in jabba.h but not exported"
-    assert L.jabba_abi_version() == 3
+    assert L.jabba_abi_version() == 4
     assert set(_lib.EXPORTS) == set(declared_functions())
 
 
@@ -58,6 +58,22 @@ def test_host_side_validation_needs_no_gpu():
     assert rc == _lib.JABBA_EINVAL
     rc = L.jabba_digitize(None, None, None, 10, 0.5, 1.0, 0, None, None, C.byref(d), None, 0, None)
     assert rc == _lib.JABBA_EINVAL
+
+
+def test_reconstruct_needs_its_workspace():
+    # the fill call takes the reconstruct workspace (it orders the series
+    # there): missing or short, it is refused before any launch
+    from paper_2401_00109_amd import _lib
+    L = _lib.lib()
+    n = C.c_size_t()
+    assert L.jabba_reconstruct_workspace(1000, C.byref(n)) == 0 and n.value > 0
+    fake = C.c_void_p(256)  # never dereferenced on the host
+    d = _lib.Dict(capacity=4, center_len=256, center_inc=256)
+    args = [fake, fake, fake, 1000, fake, C.byref(d), fake, fake, None, None, None, None]
+    assert L.jabba_reconstruct(*args, None, n.value, None) == _lib.JABBA_ENOMEM
+    assert L.jabba_reconstruct(*args, fake, n.value - 1, None) == _lib.JABBA_ENOMEM
+    assert L.jabba_reconstruct(fake, fake, fake, 0, fake, C.byref(d), fake, fake, None, None, None, None, None, 0,
+                               None) == 0  # no series: nothing to do
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
