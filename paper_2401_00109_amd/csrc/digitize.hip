@@ -20,6 +20,7 @@
 // definition, so local starts, blocks and symbols are bit-identical to it.
 #include "common.h"
 #include "sort_plan.h"
+#include "lane_ops.h"
 
 namespace jabba {
 
@@ -1010,6 +1011,38 @@ struct SumLds {
     uint32_t cnt[kBlkCap];
 };
 
+// lane ^ m for a stride m that the unrolled loops below fix at compile time
+__device__ __forceinline__ uint32_t xor_lane_m(uint32_t v, int m) {
+    switch (m) {
+        case 1: return xor_lane<1>(v);
+        case 2: return xor_lane<2>(v);
+        case 4: return xor_lane<4>(v);
+        case 8: return xor_lane<8>(v);
+        case 16: return xor_lane<16>(v);
+        default: return xor_lane<32>(v);
+    }
+}
+
+// One step of the segmented inclusive scan: each lane takes the partial sums
+// of the lane Ctrl selects and adds them when that lane is in its run (the
+// keys are sorted, so runs are contiguous); lanes without a source read a
+// segment that matches none.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void seg_scan_step(uint32_t seg, double &v, long long &l, uint32_t &c) {
+    const uint32_t ys = dpp_keep<Ctrl, RowMask>(0xFFFFFFFFu, seg);
+    const uint32_t v0 = dpp_keep<Ctrl, RowMask>(0u, (uint32_t)__double2loint(v));
+    const uint32_t v1 = dpp_keep<Ctrl, RowMask>(0u, (uint32_t)__double2hiint(v));
+    const uint64_t lu = (uint64_t)l;
+    const uint32_t l0 = dpp_keep<Ctrl, RowMask>(0u, (uint32_t)lu);
+    const uint32_t l1 = dpp_keep<Ctrl, RowMask>(0u, (uint32_t)(lu >> 32));
+    const uint32_t yc = dpp_keep<Ctrl, RowMask>(0u, c);
+    if (ys == seg) {
+        v = v + __hiloint2double((int)v1, (int)v0);
+        l += (long long)(((uint64_t)l1 << 32) | l0);
+        c += yc;
+    }
+}
+
 __device__ __forceinline__ int64_t block_starts(const int64_t *__restrict__ cuts, const uint32_t *__restrict__ sidx,
                                                 int64_t blk) {
     return (int64_t)sidx[cuts[blk + 1]] - (int64_t)sidx[cuts[blk]];
@@ -1059,13 +1092,14 @@ __global__ __launch_bounds__(256) void k_block_sums(const int64_t *__restrict__ 
 #pragma unroll
         for (int r = 0; r < kSumStage; ++r) {
             if (c0 + r * kWave >= hi) break;
-            // ascending bitonic sort of the 64 keys across the lanes
+            // ascending bitonic sort of the 64 keys across the lanes (the
+            // partners move through DPP and the permlane swaps, not LDS)
             uint32_t k = key[r];
 #pragma unroll
             for (int size = 2; size <= kWave; size <<= 1) {
 #pragma unroll
                 for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                    const uint32_t o = __shfl_xor(k, stride);
+                    const uint32_t o = xor_lane_m(k, stride);
                     const bool up = (lane & size) == 0 || size == kWave;
                     const bool low = (lane & stride) == 0;
                     k = (low == up) ? (k < o ? k : o) : (k < o ? o : k);
@@ -1076,21 +1110,17 @@ __global__ __launch_bounds__(256) void k_block_sums(const int64_t *__restrict__ 
             double v = __shfl(iv[r], src);
             long long l = (long long)__shfl(lv[r], src);
             uint32_t c = k != kNone ? 1u : 0u;
-            // segmented inclusive scan over runs of equal seg
-#pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const double yv = __shfl_up(v, d);
-                const long long yl = __shfl_up(l, d);
-                const uint32_t yc = __shfl_up(c, d);
-                const uint32_t ys = __shfl_up(seg, d);
-                if (lane >= d && ys == seg) {
-                    v = v + yv;
-                    l += yl;
-                    c += yc;
-                }
-            }
-            const uint32_t nx = __shfl_down(seg, 1);
-            if (k != kNone && (lane == kWave - 1 || nx != seg)) {
+            // segmented inclusive scan over runs of equal seg: row shifts by
+            // 1, 2, 4 and 8, then lane 15 of rows 0 and 2 into rows 1 and 3,
+            // and lane 31 into rows 2 and 3
+            seg_scan_step<0x111, 0xF>(seg, v, l, c);
+            seg_scan_step<0x112, 0xF>(seg, v, l, c);
+            seg_scan_step<0x114, 0xF>(seg, v, l, c);
+            seg_scan_step<0x118, 0xF>(seg, v, l, c);
+            seg_scan_step<0x142, 0xA>(seg, v, l, c);
+            seg_scan_step<0x143, 0xC>(seg, v, l, c);
+            const uint32_t nx = next_lane(seg, 0xFFFFFFFFu);  // the last lane ends its run
+            if (k != kNone && nx != seg) {
                 S.inc[seg] = S.inc[seg] + v;
                 S.len[seg] += (unsigned long long)l;
                 S.cnt[seg] += c;
