@@ -6,6 +6,7 @@
 #include <stddef.h>
 
 #include "jabba.h"
+#include "lane_ops.h"
 #include "sort_plan.h"
 
 namespace jabba {
@@ -136,8 +137,13 @@ __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src); }
 // (lane pairs (0,1), (2,3), ..., then pairs of pairs).  Floating-point
 // addition is commutative, so every lane ends with the same bits.
 __device__ __forceinline__ double wave_tree_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m);
+    // step m: every lane adds the value of lane ^ m (lane moves in the VALU)
+    v = v + xor_lane_f64<1>(v);
+    v = v + xor_lane_f64<2>(v);
+    v = v + xor_lane_f64<4>(v);
+    v = v + xor_lane_f64<8>(v);
+    v = v + xor_lane_f64<16>(v);
+    v = v + xor_lane_f64<32>(v);
     return v;
 }
 
@@ -155,9 +161,14 @@ __device__ __forceinline__ double block_tree_1024(double a0, double a1, double a
 }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-    return v;
+    uint64_t u = (uint64_t)v;
+    u += xor_lane_u64<1>(u);
+    u += xor_lane_u64<2>(u);
+    u += xor_lane_u64<4>(u);
+    u += xor_lane_u64<8>(u);
+    u += xor_lane_u64<16>(u);
+    u += xor_lane_u64<32>(u);
+    return (int64_t)u;
 }
 
 __device__ __forceinline__ void set_status(int32_t *st, int32_t bit) {

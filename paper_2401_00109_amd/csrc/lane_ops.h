@@ -40,6 +40,18 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
     }
 }
 
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v) {
+    const uint32_t lo = xor_lane<M>((uint32_t)v);
+    const uint32_t hi = xor_lane<M>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane_f64(double v) {
+    return __longlong_as_double((long long)xor_lane_u64<M>((uint64_t)__double_as_longlong(v)));
+}
+
 // value of lane + 1; the last lane receives `last`
 __device__ __forceinline__ uint32_t next_lane(uint32_t v, uint32_t last) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)last, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
