@@ -139,7 +139,7 @@ def order_class(pieces):
     return 32 - lg if lg < 32 else 0
 
 
-def series_order(piece_counts, threads=256, blocks=3):
+def series_order(piece_counts, threads=256):
     cls = [order_class(p) for p in piece_counts]
     hist = np.bincount(cls, minlength=34)
     base = np.concatenate([[0], np.cumsum(hist)[:-1]])
